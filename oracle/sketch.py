@@ -1,0 +1,162 @@
+"""Sketching operators of the oracle: CountSketch (Clarkson-Woodruff) and the
+Gaussian sketch, in float64.
+
+TEST INFRASTRUCTURE ONLY: nothing in the product path may import this module.
+
+Paper: Sec. 1.2 lists the three sketch-and-solve steps (generate S, form SA and
+Sb, solve on SA); Sec. 1.2.2 defines the Clarkson-Woodruff sketch as a sparse
+matrix combined with a random sign matrix (one nonzero per column of S);
+Sec. 1.2.1 defines the Gaussian sketch by i.i.d. Gaussian entries; Sec. 1.3
+fixes the shapes S in R^{d x m}, A in R^{m x n}.
+
+Readings fixed here (the paper is silent on them):
+  * hash layout: row i uses Philox4x32-10 block j = i >> 1 with counter
+    (j mod 2^32, j >> 32, 0, 0) and key (seed mod 2^32, seed >> 32); lane
+    i & 1 takes words (2*lane, 2*lane+1) as (w_h, w_s).  The bucket is the
+    multiply-shift reduction h = (w_h * d) >> 32 and the sign is +1 when the
+    top bit of w_s is clear, else -1.  Entries of S are +-1 with no scale.
+  * Gaussian sketch: entry G[k, i] is the table value T[q] where q is one
+    byte of Philox4x32-10 at counter (i mod 2^32, i >> 32, k >> 4, 1) and key
+    seed; byte (k & 15) of the little-endian 16-byte output.  T[q] is the
+    inverse normal CDF at the midpoint (q + 1/2) / 256 rounded to bfloat16
+    (round to nearest even).  SA = d^{-1/2} G bf16(A), Sb = d^{-1/2} G bf16(b).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.sparse as sp
+from scipy.special import ndtri
+
+from .philox import philox4x32
+
+TAG_COUNT = 0
+TAG_GAUSS = 1
+
+
+# --------------------------------------------------------------------------
+# CountSketch hash
+# --------------------------------------------------------------------------
+
+def countsketch_hash(seed: int, d: int, i0: int, count: int):
+    """Bucket h(i) in [0, d) and sign s(i) in {+1, -1} for rows i0 .. i0+count-1.
+
+    Returns (h uint32[count], s int8[count]).
+    """
+    if count == 0:
+        return np.zeros(0, np.uint32), np.zeros(0, np.int8)
+    i = np.uint64(i0) + np.arange(count, dtype=np.uint64)
+    j = i >> np.uint64(1)
+    lane = (i & np.uint64(1)).astype(bool)
+    c0 = (j & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    c1 = (j >> np.uint64(32)).astype(np.uint32)
+    zero = np.zeros_like(c0)
+    w0, w1, w2, w3 = philox4x32(c0, c1, zero + TAG_COUNT, zero, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    w_h = np.where(lane, w2, w0)
+    w_s = np.where(lane, w3, w1)
+    h = ((w_h.astype(np.uint64) * np.uint64(d)) >> np.uint64(32)).astype(np.uint32)
+    s = (1 - 2 * (w_s >> np.uint32(31)).astype(np.int16)).astype(np.int8)
+    return h, s
+
+
+def countsketch_matrix(seed: int, d: int, m: int) -> sp.csr_matrix:
+    """The sketch S in R^{d x m} as a sparse matrix: S[h(i), i] = s(i)."""
+    h, s = countsketch_hash(seed, d, 0, m)
+    return sp.csr_matrix((s.astype(np.float64), (h.astype(np.int64), np.arange(m))), shape=(d, m))
+
+
+def countsketch_apply(A, b, seed: int, d: int):
+    """SA = S A and Sb = S b in float64 with S from countsketch_matrix.
+
+    A may be a dense (m, n) array or a scipy sparse matrix; its values are
+    widened to float64 first, so the result is the exact product of the
+    stored inputs up to float64 rounding.  b may be None.
+    """
+    m = A.shape[0]
+    S = countsketch_matrix(seed, d, m)
+    if sp.issparse(A):
+        SA = (S @ A.astype(np.float64)).toarray()
+    else:
+        SA = S @ np.asarray(A, dtype=np.float64)
+    Sb = None if b is None else S @ np.asarray(b, dtype=np.float64)
+    return np.asarray(SA), Sb
+
+
+def countsketch_apply_loop(A, b, seed: int, d: int):
+    """The same sketch as an explicit loop over rows in ascending order.
+
+    For each row i: SA[h(i), :] += s(i) A[i, :], Sb[h(i)] += s(i) b[i].
+    Slow; for small inputs only.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    h, s = countsketch_hash(seed, d, 0, m)
+    SA = np.zeros((d, n))
+    Sb = np.zeros(d)
+    for i in range(m):
+        SA[h[i], :] += s[i] * A[i, :]
+        if b is not None:
+            Sb[h[i]] += s[i] * float(b[i])
+    return SA, (None if b is None else Sb)
+
+
+# --------------------------------------------------------------------------
+# bfloat16 rounding and the Gaussian table
+# --------------------------------------------------------------------------
+
+def bf16_round(x) -> np.ndarray:
+    """Round float64 values to the nearest bfloat16 (8 significant bits),
+    ties to even, returned as float64.  Values here stay in the normal range
+    of bfloat16; zero maps to zero."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = x != 0
+    e = np.floor(np.log2(np.abs(x[nz])))
+    ulp = np.exp2(e - 7.0)
+    q = x[nz] / ulp
+    # guard the log2 boundary: a mantissa in [256, 512) means e was one low
+    big = np.abs(q) >= 256.0
+    ulp = np.where(big, ulp * 2.0, ulp)
+    q = x[nz] / ulp
+    out[nz] = np.rint(q) * ulp  # np.rint rounds half to even
+    return out
+
+
+def gaussian_table() -> np.ndarray:
+    """T[q] = bf16(Phi^{-1}((q + 1/2) / 256)) for q = 0..255, float64."""
+    q = np.arange(256, dtype=np.float64)
+    return bf16_round(ndtri((q + 0.5) / 256.0))
+
+
+def gaussian_codes(seed: int, d: int, i0: int, count: int) -> np.ndarray:
+    """Byte codes q[k, i] (uint8, shape (d, count)) for columns i0..i0+count-1."""
+    i = np.uint64(i0) + np.arange(count, dtype=np.uint64)
+    c0 = (i & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    c1 = (i >> np.uint64(32)).astype(np.uint32)
+    nblk = (d + 15) // 16
+    q = np.empty((nblk * 16, count), dtype=np.uint8)
+    for kb in range(nblk):
+        c2 = np.full(count, kb, dtype=np.uint32)
+        c3 = np.full(count, TAG_GAUSS, dtype=np.uint32)
+        w = philox4x32(c0, c1, c2, c3, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+        for t in range(4):
+            for byte in range(4):
+                q[16 * kb + 4 * t + byte, :] = ((w[t] >> np.uint32(8 * byte)) & np.uint32(0xFF)).astype(np.uint8)
+    return q[:d, :]
+
+
+def gaussian_matrix(seed: int, d: int, m: int, i0: int = 0) -> np.ndarray:
+    """G[k, i] for i in [i0, i0+m) (unscaled, float64, shape (d, m))."""
+    return gaussian_table()[gaussian_codes(seed, d, i0, m)]
+
+
+def gaussian_apply(A, b, seed: int, d: int):
+    """SA = d^{-1/2} G bf16(A), Sb = d^{-1/2} G bf16(b), in float64."""
+    A = np.asarray(A, dtype=np.float64)
+    m = A.shape[0]
+    G = gaussian_matrix(seed, d, m)
+    scale = 1.0 / math.sqrt(d)
+    SA = scale * (G @ bf16_round(A))
+    Sb = None if b is None else scale * (G @ bf16_round(np.asarray(b, dtype=np.float64)))
+    return SA, Sb

@@ -1,0 +1,93 @@
+"""Sketch-and-solve and sketch-and-precondition least squares, float64.
+
+TEST INFRASTRUCTURE ONLY: nothing in the product path may import this module.
+
+* sketch_and_solve: the three steps of Sec. 1.2 for the problem of Sec. 1.3:
+  draw S, form SA and Sb, and solve min ||SA x - Sb|| by Householder QR of
+  [SA | Sb] and back substitution.  This is the plain (SAS) answer x_0.
+* sap_sas: the sketch-and-precondition solver named in Sec. 2.1 (SAP-SAS):
+  start from the sketch-and-solve x_0, then run LSQR on A R^{-1} (applied as
+  v -> A (R^{-1} v) and u -> R^{-T} (A^T u), never formed) against the
+  residual r_0 = b - A x_0, and return x = x_0 + R^{-1} dy.
+
+Stop rule (reading C-8): with sigma_hat = 1 - sqrt(n / d), the lower edge of
+the Marchenko-Pastur law for the singular values of the preconditioned
+operator, stop when ||Abar^T r_k|| / ||r_k|| <= rtol * sigma_hat; this bounds
+the residual error ||A (x_k - x*)|| / ||b - A x*|| by about rtol.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+from .lsqr import lsqr
+from .qr import (back_substitution, forward_substitution_transposed,
+                 householder_qr_augmented, rank_deficient)
+from .sketch import countsketch_apply, gaussian_apply
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    x0: np.ndarray
+    R: np.ndarray
+    c: np.ndarray
+    rho: float
+    iters: int
+    rank_deficient: bool
+    rnorm: float = float("nan")
+    arnorm: float = float("nan")
+
+
+def sketch(A, b, kind: str, seed: int, d: int):
+    if kind == "count":
+        return countsketch_apply(A, b, seed, d)
+    if kind == "gaussian":
+        return gaussian_apply(A, b, seed, d)
+    raise ValueError(kind)
+
+
+def _matvec(A, x):
+    return np.asarray(A @ x, dtype=np.float64).ravel()
+
+
+def _rmatvec(A, u):
+    if sp.issparse(A):
+        return np.asarray(A.T @ u, dtype=np.float64).ravel()
+    return np.asarray(A, dtype=np.float64).T @ u
+
+
+def sigma_hat(n: int, d: int) -> float:
+    return 1.0 - math.sqrt(n / d)
+
+
+def sketch_and_solve(A, b, kind: str, seed: int, d: int, SA=None, Sb=None) -> SolveResult:
+    if SA is None:
+        SA, Sb = sketch(A, b, kind, seed, d)
+    R, c, rho, _, _ = householder_qr_augmented(SA, Sb)
+    rd = rank_deficient(R)
+    x0 = back_substitution(R, c)
+    return SolveResult(x0, x0, R, c, rho, 0, rd)
+
+
+def sap_sas(A, b, kind: str, seed: int, d: int, max_iters: int, rtol: float = 0.0,
+            SA=None, Sb=None) -> SolveResult:
+    """SAP-SAS; rtol = 0 runs exactly max_iters LSQR iterations."""
+    base = sketch_and_solve(A, b, kind, seed, d, SA, Sb)
+    R = base.R
+    n = R.shape[0]
+    if sp.issparse(A):
+        Af = A.astype(np.float64)
+    else:
+        Af = np.asarray(A, dtype=np.float64)
+    bf = np.asarray(b, dtype=np.float64)
+    r0 = bf - _matvec(Af, base.x0)
+    res = lsqr(lambda v: _matvec(Af, back_substitution(R, v)),
+               lambda u: forward_substitution_transposed(R, _rmatvec(Af, u)),
+               r0, n, max_iters, stop_ratio=rtol * sigma_hat(n, d))
+    x = base.x0 + back_substitution(R, res.x)
+    return SolveResult(x, base.x0, R, base.c, base.rho, res.iters, base.rank_deficient,
+                       res.rnorm, res.arnorm)

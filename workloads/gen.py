@@ -1,0 +1,176 @@
+"""Generators for the five least-squares workloads and the paper's own
+benchmark family.
+
+Every generator takes an explicit seed and draws from numpy's default_rng, so
+each input is reproducible.  Values are drawn in float64 and rounded once to
+the stored dtype; the stored values *are* the problem (the oracle widens them
+back to float64).
+
+Workloads (sizes are the defaults; tests pass smaller ones):
+  plain FP64 sketch-and-solve   dense_gaussian(20000, 50, float64), d = 200
+  ill-conditioned FP32          dense_ill_conditioned(4194304, 256), d = 1024
+  sparse CSR FP32               sparse_csr(2**24, 1000), d = 4000
+  Gaussian sketch on MFMA       dense_scaled_columns(262144, 512), d = 2048
+  serving mix                   serving_requests(10000, 2000.0) + dense_gaussian per request
+  paper benchmark (Sec. 3.1)    paper_benchmark(m, 1000, cond 1e10, beta 1e-10)
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+DATA_SEED_BASE = 1000
+SKETCH_SEED = 42
+
+
+@dataclass
+class Dense:
+    A: np.ndarray
+    b: np.ndarray
+    x_true: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+
+@dataclass
+class Sparse:
+    A: sp.csr_matrix
+    b: np.ndarray
+    x_true: np.ndarray
+    meta: dict = field(default_factory=dict)
+
+
+def dense_gaussian(m: int, n: int, seed: int, noise: float = 1e-3, dtype=np.float64) -> Dense:
+    """A_ij ~ N(0,1), x_true ~ N(0, I), b = A x_true + noise * N(0, I)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)).astype(dtype)
+    x = rng.standard_normal(n)
+    b = (A.astype(np.float64) @ x + noise * rng.standard_normal(m)).astype(dtype)
+    return Dense(A, b, x, {"kind": "dense_gaussian", "m": m, "n": n, "seed": seed, "noise": noise})
+
+
+def random_orthogonal(n: int, rng) -> np.ndarray:
+    """Q factor of an n x n Gaussian matrix with the signs fixed so diag(R) > 0."""
+    Q, R = np.linalg.qr(rng.standard_normal((n, n)))
+    return Q * np.sign(np.diag(R))
+
+
+def dense_ill_conditioned(m: int, n: int, seed: int, cond: float = 1e6, rel_noise: float = 1e-4,
+                          dtype=np.float32, block: int = 1 << 16) -> Dense:
+    """A = G diag(sigma) V^T with G Gaussian, sigma log-spaced 1 .. 1/cond, V orthogonal.
+
+    b = A x_true + rel_noise * (||A x_true|| / ||z||) z with z ~ N(0, I_m).
+    A is built in float64 row blocks and rounded to dtype; b is computed from
+    the rounded A.
+    """
+    rng = np.random.default_rng(seed)
+    sigma = np.logspace(0.0, -np.log10(cond), n)
+    V = random_orthogonal(n, rng)
+    W = (sigma[:, None] * V.T)  # diag(sigma) V^T
+    x = rng.standard_normal(n)
+    A = np.empty((m, n), dtype=dtype)
+    b0 = np.empty(m)
+    for r0 in range(0, m, block):
+        r1 = min(m, r0 + block)
+        G = rng.standard_normal((r1 - r0, n))
+        A[r0:r1] = (G @ W).astype(dtype)
+        b0[r0:r1] = A[r0:r1].astype(np.float64) @ x
+    z = rng.standard_normal(m)
+    b = (b0 + rel_noise * (np.linalg.norm(b0) / np.linalg.norm(z)) * z).astype(dtype)
+    return Dense(A, b, x, {"kind": "dense_ill_conditioned", "m": m, "n": n, "seed": seed,
+                           "cond": cond, "rel_noise": rel_noise})
+
+
+def dense_scaled_columns(m: int, n: int, seed: int, decades: float = 3.0, noise: float = 1e-3,
+                         dtype=np.float32) -> Dense:
+    """A_ij ~ N(0,1) * 10^(-decades * j / (n-1)), b = A x_true + noise * N(0, I)."""
+    rng = np.random.default_rng(seed)
+    scale = 10.0 ** (-decades * np.arange(n) / max(n - 1, 1))
+    A = np.empty((m, n), dtype=dtype)
+    blk = 1 << 16
+    for r0 in range(0, m, blk):
+        r1 = min(m, r0 + blk)
+        A[r0:r1] = (rng.standard_normal((r1 - r0, n)) * scale).astype(dtype)
+    x = rng.standard_normal(n)
+    b = (A.astype(np.float64) @ x + noise * rng.standard_normal(m)).astype(dtype)
+    return Dense(A, b, x, {"kind": "dense_scaled_columns", "m": m, "n": n, "seed": seed})
+
+
+def sparse_csr(m: int, n: int, seed: int, nnz_per_col: int = 1000, dense_block: int = 1000,
+               noise: float = 1e-3, dtype=np.float32) -> Sparse:
+    """Each column gets nnz_per_col distinct uniformly random rows with N(0,1)
+    values; a dense N(0,1) block on rows/columns [0, dense_block) makes A full
+    rank.  CSR with int32 indices sorted within rows; duplicates are summed."""
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    k = min(nnz_per_col, m)
+    for j in range(n):
+        r = rng.choice(m, size=k, replace=False)
+        rows.append(r)
+        cols.append(np.full(k, j))
+        vals.append(rng.standard_normal(k))
+    db = min(dense_block, m, n)
+    if db > 0:
+        rr, cc = np.meshgrid(np.arange(db), np.arange(db), indexing="ij")
+        rows.append(rr.ravel())
+        cols.append(cc.ravel())
+        vals.append(rng.standard_normal(db * db))
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(m, n)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    A = sp.csr_matrix((A.data.astype(dtype), A.indices.astype(np.int32), A.indptr.astype(np.int32)),
+                      shape=(m, n))
+    x = rng.standard_normal(n)
+    b = (A.astype(np.float64) @ x + noise * rng.standard_normal(m)).astype(dtype)
+    return Sparse(A, b, x, {"kind": "sparse_csr", "m": m, "n": n, "seed": seed, "nnz": int(A.nnz)})
+
+
+def serving_requests(count: int, rate: float, seed: int, log2_m=(12.0, 20.0),
+                     n_choices=(16, 32, 64, 128, 256), d_factor: int = 4):
+    """Poisson arrivals at `rate` per second; m = floor(2^U[lo, hi]); n uniform
+    over n_choices; d = d_factor * n.  Returns a list of dicts sorted by arrival."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    ms = np.floor(2.0 ** rng.uniform(log2_m[0], log2_m[1], size=count)).astype(np.int64)
+    ns = rng.choice(np.asarray(n_choices), size=count)
+    seeds = rng.integers(0, 2**31 - 1, size=count)
+    return [{"id": i, "t": float(t[i]), "m": int(ms[i]), "n": int(ns[i]), "d": int(d_factor * ns[i]),
+             "seed": int(seeds[i])} for i in range(count)]
+
+
+def paper_benchmark(m: int, n: int, seed: int, cond: float = 1e10, beta: float = 1e-10) -> Dense:
+    """Sec. 3.1 family: A = U diag(sigma) V^T with Haar U (m x n) and V (n x n),
+    sigma log-spaced 1 .. 1/cond; b = A x + beta r_perp with r_perp a unit
+    vector orthogonal to range(A), so the optimal residual norm is beta."""
+    rng = np.random.default_rng(seed)
+    U, R = np.linalg.qr(rng.standard_normal((m, n)))
+    U = U * np.sign(np.diag(R))
+    V = random_orthogonal(n, rng)
+    sigma = np.logspace(0.0, -np.log10(cond), n)
+    A = (U * sigma) @ V.T
+    x = rng.standard_normal(n)
+    x /= np.linalg.norm(x)
+    z = rng.standard_normal(m)
+    z -= U @ (U.T @ z)
+    z /= np.linalg.norm(z)
+    b = A @ x + beta * z
+    return Dense(A, b, x, {"kind": "paper_benchmark", "m": m, "n": n, "seed": seed,
+                           "cond": cond, "beta": beta})
+
+
+# Named workload configurations (sizes, sketch, solver settings).
+CONFIGS = {
+    "plain_fp64_20000x50": dict(gen="dense_gaussian", m=20000, n=50, d=200, dtype="f64",
+                                sketch="count", refine=0, seed=DATA_SEED_BASE + 0),
+    "illcond_fp32_4194304x256": dict(gen="dense_ill_conditioned", m=4194304, n=256, d=1024,
+                                     dtype="f32", sketch="count", refine=1, iters=3,
+                                     seed=DATA_SEED_BASE + 1),
+    "csr_fp32_16777216x1000": dict(gen="sparse_csr", m=1 << 24, n=1000, d=4000, dtype="f32",
+                                   sketch="count", refine=0, seed=DATA_SEED_BASE + 2),
+    "gauss_bf16_262144x512": dict(gen="dense_scaled_columns", m=262144, n=512, d=2048, dtype="f32",
+                                  sketch="gaussian", refine=1, rtol=1e-6, seed=DATA_SEED_BASE + 3),
+    "serve_mix_10000": dict(gen="serving_requests", count=10000, rate=2000.0,
+                            seed=DATA_SEED_BASE + 4),
+}
