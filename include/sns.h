@@ -1,0 +1,182 @@
+/*
+ * sns.h - C ABI of libsns: sketch-and-solve least squares on MI355X (gfx950).
+ *
+ * The library solves the overdetermined least-squares problem
+ *     min_x || A x - b ||_2,   A in R^{m x n}, b in R^m            (Sec. 1.3, eq. 1)
+ * by the sketch-and-solve paradigm of Sec. 1.2: draw a sketch S in R^{d x m}
+ * (m >> n, n <= d), form SA and Sb, and solve the reduced problem
+ * min || SA x - Sb || (Sec. 1.3) by Householder QR of [SA | Sb] and a
+ * triangular solve.  Optionally the answer is refined with LSQR on the
+ * right-preconditioned operator A R^{-1} (the sketch-and-precondition solver
+ * SAP-SAS of Sec. 2.1).
+ *
+ * Conventions for every entry point:
+ *   - All matrix/vector pointers are DEVICE pointers (memory of the current
+ *     HIP device) unless stated otherwise.  The caller owns every buffer,
+ *     including the workspace; the library never allocates or frees device
+ *     memory on these paths and keeps no pointer after the call returns
+ *     (serving requests excepted, see sns_serve_submit).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it in order; calls return without waiting
+ *     unless documented.  Results are valid after the stream is synchronised.
+ *   - Dense matrices are row-major with leading dimension ld >= n (elements).
+ *   - Argument errors are detected on the host before anything is enqueued and
+ *     returned immediately; nothing is written in that case.
+ *   - Numerical outcomes (rank deficiency, non-finite values, non-convergence)
+ *     are reported through sns_info, written on the stream.
+ *   - Results are deterministic: the same inputs, seed and sizes give the same
+ *     bits, whatever else runs on the device.  No floating-point atomics are
+ *     used anywhere.
+ *   - Size limits: m < 2^31; CountSketch d <= 16384; QR d <= 8192 and
+ *     n <= 4096; LSQR refinement n <= 2048 with 16-byte aligned rows
+ *     (values pointer and ld * element size multiples of 16).
+ */
+#ifndef SNS_H
+#define SNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SNS_OK = 0,
+  SNS_ERR_INVALID_ARG = 1,   /* null pointer, bad enum, bad option value */
+  SNS_ERR_SHAPE = 2,         /* violates n >= 1, n <= d <= m, ld >= n, or a size limit */
+  SNS_ERR_DTYPE = 3,         /* dtype / layout / sketch combination not supported */
+  SNS_ERR_RANK_DEFICIENT = 4,/* |R_jj| <= 10 n u64 max_i |R_ii| for some j */
+  SNS_ERR_NOT_CONVERGED = 5, /* LSQR reached max_iters before the stop rule held */
+  SNS_ERR_NUMERICAL = 6,     /* non-finite value met in a norm or the factorisation */
+  SNS_ERR_OUT_OF_MEMORY = 7, /* workspace / serving pool too small */
+  SNS_ERR_QUEUE_FULL = 8,    /* serving queue full */
+  SNS_ERR_NOT_READY = 9,     /* serving request still in flight */
+  SNS_ERR_HIP = 10           /* a HIP runtime call failed */
+} sns_status;
+
+typedef enum { SNS_F32 = 0, SNS_F64 = 1 } sns_dtype;
+typedef enum { SNS_DENSE_ROWMAJOR = 0, SNS_CSR = 1 } sns_layout;
+
+/* Sketch operators (Sec. 1.2.1 and 1.2.2). */
+typedef enum {
+  SNS_SKETCH_COUNT = 0,    /* Clarkson-Woodruff CountSketch: one +-1 per column of S */
+  SNS_SKETCH_GAUSSIAN = 1  /* dense Gaussian sketch, bf16 inputs, fp32 accumulation */
+} sns_sketch_kind;
+
+/* A tall matrix.  Dense: values (m x n row-major, leading dimension ld).
+ * CSR: row_ptr[m+1] and col_idx[nnz] (int32, column indices ascending within a
+ * row), values[nnz]; ld is ignored.  `values` has the element type `dtype`. */
+typedef struct {
+  int64_t m, n;
+  sns_dtype dtype;
+  sns_layout layout;
+  const void* values;
+  int64_t ld;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  int64_t nnz;
+} sns_matrix;
+
+/* The sketch S in R^{d x m}, drawn from `seed`.
+ * CountSketch (Sec. 1.2.2): S[h(i), i] = s(i), every other entry 0, where
+ *   (w0,w1,w2,w3) = Philox4x32-10(counter (j mod 2^32, j >> 32, 0, 0),
+ *                                 key (seed mod 2^32, seed >> 32)), j = i >> 1,
+ *   lane = i & 1, h(i) = (w_{2 lane} * d) >> 32, s(i) = +1 if the top bit of
+ *   w_{2 lane + 1} is clear, else -1.
+ * Gaussian (Sec. 1.2.1): S = d^{-1/2} G with G[k, i] = T[q], q the byte
+ *   (k & 15) of Philox4x32-10(counter (i mod 2^32, i >> 32, k >> 4, 1), key as
+ *   above), T[q] = bf16(Phi^{-1}((q + 1/2) / 256)).  The product uses
+ *   bf16(A) and bf16(b) (round to nearest even). */
+typedef struct {
+  sns_sketch_kind kind;
+  int64_t d;
+  uint64_t seed;
+} sns_sketch;
+
+typedef struct {
+  int refine;      /* 0: plain sketch-and-solve; 1: SAP-SAS (LSQR on A R^{-1}) */
+  int max_iters;   /* LSQR iteration cap (refine = 1) */
+  double rtol;     /* stop when ||Abar^T r|| / ||r|| <= rtol (1 - sqrt(n/d));
+                      rtol = 0 runs exactly max_iters iterations */
+  int accum_fp64;  /* 1: accumulate the CountSketch in fp64 (fp32 inputs) */
+} sns_solve_opts;
+
+typedef struct {
+  int32_t status;          /* an sns_status */
+  int32_t iters;           /* LSQR iterations run */
+  double rel_resid_est;    /* ||Abar^T r|| / (||r|| (1 - sqrt(n/d))) at exit; 0 if refine = 0 */
+  double sketch_resid;     /* ||(Q^T Sb)[n:]||, the sketched residual norm */
+} sns_info;
+
+/* Human-readable name of a status code (static string). */
+const char* sns_status_string(int status);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int sns_version(void);
+
+/* CountSketch hash of rows i0 .. i0+count-1 (definition at sns_sketch).
+ * h: device uint32[count], s: device int8[count] (either may be NULL).
+ * Errors: SNS_ERR_SHAPE if d < 1 or d >= 2^32, count < 0. */
+sns_status sns_hash(uint64_t seed, int64_t d, int64_t i0, int64_t count,
+                    uint32_t* h, int8_t* s, void* stream);
+
+/* The 256-entry Gaussian table T used on the device, as bf16 bit patterns,
+ * copied to the HOST array out[256].  Synchronous. */
+sns_status sns_gaussian_table(uint16_t* out);
+
+/* Workspace bytes sns_sketch_apply needs for this sketch and matrix. */
+sns_status sns_sketch_workspace_size(const sns_sketch* sk, const sns_matrix* A, size_t* bytes);
+
+/* SA = S A and Sb = S b (step 2 of Sec. 1.2).
+ * SA: device d x n row-major (leading dimension n) of A's dtype, fully
+ * overwritten (empty buckets give zero rows).  b and Sb may both be NULL;
+ * otherwise b has m entries and Sb d entries of A's dtype.
+ * CountSketch: one deterministic pass over [A | b]; rows are grouped by bucket
+ * with a stable counting sort and each bucket is reduced in a fixed order.
+ * accum_fp64 (from opts, may be NULL) selects fp64 accumulation for fp32 A.
+ * Gaussian: fp32 A only (SNS_ERR_DTYPE otherwise); computed on the matrix
+ * cores as bf16 x bf16 products with fp32 accumulation.
+ * Errors: SNS_ERR_INVALID_ARG (NULL sk/A/SA/workspace, b and Sb not both set
+ * or both NULL), SNS_ERR_SHAPE (n < 1, d < 1, m < 1, ld < n, m >= 2^31),
+ * SNS_ERR_OUT_OF_MEMORY (ws_bytes too small). */
+sns_status sns_sketch_apply(const sns_sketch* sk, const sns_matrix* A, const void* b,
+                            void* SA, void* Sb, const sns_solve_opts* opts,
+                            void* workspace, size_t ws_bytes, void* stream);
+
+/* Householder QR of the augmented d x (n+1) matrix [SA | Sb] (fp64) and the
+ * triangular solve R x0 = c with c = (Q^T Sb)[:n] (step 3 of Sec. 1.2).
+ * SA: device d x n row-major (ld_sa >= n) and Sb: device d, both of `dtype`.
+ * Outputs: x0 device fp64[n]; R (may be NULL) device fp64 n x n row-major,
+ * upper triangle with the LAPACK sign convention (beta = -sign(alpha)||x||),
+ * strictly lower part zero; info (host pointer, may be NULL) receives status
+ * (SNS_ERR_RANK_DEFICIENT if |R_jj| <= 10 n u64 max|R_ii|) and sketch_resid.
+ * Requires n <= d.  `info` is written by the stream: synchronise before
+ * reading it. */
+sns_status sns_qr_solve_workspace_size(int64_t d, int64_t n, size_t* bytes);
+sns_status sns_qr_solve(int64_t d, int64_t n, sns_dtype dtype, const void* SA, int64_t ld_sa,
+                        const void* Sb, double* x0, double* R, sns_info* info,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+/* Workspace bytes sns_lstsq needs. */
+sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
+                                    const sns_solve_opts* opts, size_t* bytes);
+
+/* Solve min ||A x - b|| (Sec. 1.3): sketch (Sec. 1.2), QR + triangular solve,
+ * and with opts->refine = 1 the SAP-SAS refinement (Sec. 2.1): LSQR on
+ * A R^{-1} from r0 = b - A x0, x = x0 + R^{-1} dy.  Every product with A
+ * accumulates in fp64; n-vectors are fp64; m-vectors are stored in A's dtype.
+ * b: device, m entries of A's dtype.  x: device fp64[n].
+ * info: HOST pointer (pinned memory recommended) or NULL; written on the
+ * stream, valid after synchronising it.
+ * Errors: as sns_sketch_apply, plus SNS_ERR_INVALID_ARG for max_iters < 0 or
+ * rtol < 0. */
+sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, double* x,
+                     const sns_solve_opts* opts, void* workspace, size_t ws_bytes,
+                     sns_info* info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNS_H */

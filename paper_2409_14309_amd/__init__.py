@@ -1,0 +1,47 @@
+"""Sketch-and-solve least squares on MI355X (gfx950).
+
+The compute lives in libsns.so (HIP); this package is its Python binding.
+Names follow the C ABI of include/sns.h.  Convenience wrappers (`sketch`,
+`lstsq`) allocate the workspace with torch and call the ABI.
+"""
+from __future__ import annotations
+
+from ._binding import (SNS_CSR, SNS_DENSE_ROWMAJOR, SNS_F32, SNS_F64, SNS_SKETCH_COUNT,  # noqa: F401
+                       SNS_SKETCH_GAUSSIAN, Info, Matrix, Sketch, SnsError, SolveOpts, csr, dense,
+                       exported_symbols, load, opts, sketch_desc, sns_gaussian_table, sns_hash,
+                       sns_lstsq, sns_lstsq_workspace_size, sns_qr_solve,
+                       sns_qr_solve_workspace_size, sns_sketch_apply, sns_sketch_workspace_size,
+                       sns_status_string, sns_version)
+
+
+def _workspace(nbytes: int, device):
+    import torch
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def sketch(A, b=None, kind: str = "count", d: int = None, seed: int = 42, accum_fp64: bool = False,
+           stream=None):
+    """SA, Sb = S A, S b for a dense device tensor A (and optional b)."""
+    import torch
+    sk = sketch_desc(kind, d, seed)
+    M = dense(A)
+    ws = _workspace(sns_sketch_workspace_size(sk, M), A.device)
+    SA = torch.empty((d, A.shape[1]), dtype=A.dtype, device=A.device)
+    Sb = torch.empty(d, dtype=A.dtype, device=A.device) if b is not None else None
+    sns_sketch_apply(sk, M, b, SA, Sb, ws, opts(accum_fp64=int(accum_fp64)), stream)
+    return SA, Sb
+
+
+def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine: bool = False,
+          max_iters: int = 100, rtol: float = 1e-6, accum_fp64: bool = False, stream=None):
+    """x (float64 device tensor) and Info for min ||A x - b||."""
+    import torch
+    sk = sketch_desc(kind, d, seed)
+    M = dense(A)
+    o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0, int(accum_fp64))
+    ws = _workspace(sns_lstsq_workspace_size(sk, M, o), A.device)
+    x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+    info = Info()
+    sns_lstsq(sk, M, b, x, o, ws, info, stream)
+    (stream or torch.cuda.current_stream()).synchronize()
+    return x, info

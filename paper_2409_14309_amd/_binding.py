@@ -1,0 +1,211 @@
+"""ctypes binding of libsns (the C ABI declared in include/sns.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+buffers are torch tensors (their data_ptr() is passed); streams default to
+torch's current stream.  A missing library raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsns.so")
+
+SNS_OK = 0
+STATUS_NAMES = ["SNS_OK", "SNS_ERR_INVALID_ARG", "SNS_ERR_SHAPE", "SNS_ERR_DTYPE",
+                "SNS_ERR_RANK_DEFICIENT", "SNS_ERR_NOT_CONVERGED", "SNS_ERR_NUMERICAL",
+                "SNS_ERR_OUT_OF_MEMORY", "SNS_ERR_QUEUE_FULL", "SNS_ERR_NOT_READY", "SNS_ERR_HIP"]
+SNS_F32, SNS_F64 = 0, 1
+SNS_DENSE_ROWMAJOR, SNS_CSR = 0, 1
+SNS_SKETCH_COUNT, SNS_SKETCH_GAUSSIAN = 0, 1
+
+
+class SnsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{where}: {name}")
+
+
+class Matrix(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("dtype", C.c_int), ("layout", C.c_int),
+                ("values", C.c_void_p), ("ld", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col_idx", C.c_void_p), ("nnz", C.c_int64)]
+
+
+class Sketch(C.Structure):
+    _fields_ = [("kind", C.c_int), ("d", C.c_int64), ("seed", C.c_uint64)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("refine", C.c_int), ("max_iters", C.c_int), ("rtol", C.c_double),
+                ("accum_fp64", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("rel_resid_est", C.c_double),
+                ("sketch_resid", C.c_double)]
+
+
+_lib = None
+
+_SIGS = {
+    "sns_status_string": (C.c_char_p, [C.c_int]),
+    "sns_version": (C.c_int, []),
+    "sns_hash": (C.c_int, [C.c_uint64, C.c_int64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                           C.c_void_p]),
+    "sns_gaussian_table": (C.c_int, [C.c_void_p]),
+    "sns_sketch_workspace_size": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix),
+                                            C.POINTER(C.c_size_t)]),
+    "sns_sketch_apply": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix), C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_size_t,
+                                   C.c_void_p]),
+    "sns_qr_solve_workspace_size": (C.c_int, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "sns_qr_solve": (C.c_int, [C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.POINTER(Info), C.c_void_p, C.c_size_t,
+                               C.c_void_p]),
+    "sns_lstsq_workspace_size": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix),
+                                           C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]),
+    "sns_lstsq": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix), C.c_void_p, C.c_void_p,
+                            C.POINTER(SolveOpts), C.c_void_p, C.c_size_t, C.POINTER(Info),
+                            C.c_void_p]),
+}
+
+
+def load(path: str | None = None):
+    """Load libsns.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libsns.so not built ({p}); run `python -m paper_2409_14309_amd.build`")
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(status: int, where: str):
+    if status != SNS_OK:
+        raise SnsError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is None:
+        return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return SNS_F32
+    if t.dtype == torch.float64:
+        return SNS_F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def dense(A) -> Matrix:
+    """Describe a 2-D device tensor (row-major, unit column stride) as sns_matrix."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be 2-D with unit column stride")
+    return Matrix(A.shape[0], A.shape[1], _dtype_code(A), SNS_DENSE_ROWMAJOR, A.data_ptr(),
+                  A.stride(0), None, None, 0)
+
+
+def csr(row_ptr, col_idx, values, m: int, n: int) -> Matrix:
+    return Matrix(m, n, _dtype_code(values), SNS_CSR, values.data_ptr(), 0, row_ptr.data_ptr(),
+                  col_idx.data_ptr(), values.numel())
+
+
+def sketch_desc(kind: str, d: int, seed: int) -> Sketch:
+    return Sketch(SNS_SKETCH_COUNT if kind == "count" else SNS_SKETCH_GAUSSIAN, d, seed)
+
+
+def opts(refine: int = 0, max_iters: int = 0, rtol: float = 0.0, accum_fp64: int = 0) -> SolveOpts:
+    return SolveOpts(refine, max_iters, rtol, accum_fp64)
+
+
+# ---------------------------------------------------------------- calls ----
+
+def sns_version() -> int:
+    return load().sns_version()
+
+
+def sns_status_string(status: int) -> str:
+    return load().sns_status_string(status).decode()
+
+
+def sns_hash(seed: int, d: int, i0: int, count: int, h=None, s=None, stream=None):
+    _check(load().sns_hash(seed, d, i0, count, _ptr(h), _ptr(s), _stream(stream)), "sns_hash")
+
+
+def sns_gaussian_table():
+    import numpy as np
+    out = np.zeros(256, dtype=np.uint16)
+    _check(load().sns_gaussian_table(out.ctypes.data_as(C.c_void_p)), "sns_gaussian_table")
+    return out
+
+
+def sns_sketch_workspace_size(sk: Sketch, A: Matrix) -> int:
+    n = C.c_size_t(0)
+    _check(load().sns_sketch_workspace_size(C.byref(sk), C.byref(A), C.byref(n)),
+           "sns_sketch_workspace_size")
+    return n.value
+
+
+def sns_sketch_apply(sk: Sketch, A: Matrix, b, SA, Sb, workspace, opt: SolveOpts | None = None,
+                     stream=None):
+    _check(load().sns_sketch_apply(C.byref(sk), C.byref(A), _ptr(b), _ptr(SA), _ptr(Sb),
+                                   C.byref(opt) if opt is not None else None, _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(), _stream(stream)),
+           "sns_sketch_apply")
+
+
+def sns_qr_solve_workspace_size(d: int, n: int) -> int:
+    b = C.c_size_t(0)
+    _check(load().sns_qr_solve_workspace_size(d, n, C.byref(b)), "sns_qr_solve_workspace_size")
+    return b.value
+
+
+def sns_qr_solve(d: int, n: int, SA, Sb, x0, R, workspace, info: Info | None = None,
+                 stream=None):
+    _check(load().sns_qr_solve(d, n, _dtype_code(SA), _ptr(SA), SA.stride(0), _ptr(Sb), _ptr(x0),
+                               _ptr(R), C.byref(info) if info is not None else None,
+                               _ptr(workspace), workspace.numel() * workspace.element_size(),
+                               _stream(stream)), "sns_qr_solve")
+
+
+def sns_lstsq_workspace_size(sk: Sketch, A: Matrix, opt: SolveOpts) -> int:
+    b = C.c_size_t(0)
+    _check(load().sns_lstsq_workspace_size(C.byref(sk), C.byref(A), C.byref(opt), C.byref(b)),
+           "sns_lstsq_workspace_size")
+    return b.value
+
+
+def sns_lstsq(sk: Sketch, A: Matrix, b, x, opt: SolveOpts, workspace, info: Info | None = None,
+              stream=None):
+    _check(load().sns_lstsq(C.byref(sk), C.byref(A), _ptr(b), _ptr(x), C.byref(opt),
+                            _ptr(workspace), workspace.numel() * workspace.element_size(),
+                            C.byref(info) if info is not None else None, _stream(stream)),
+           "sns_lstsq")

@@ -1,0 +1,245 @@
+// C ABI of libsns: argument checks, workspace layout and dispatch.  Every
+// entry point validates on the host before enqueuing anything.
+#include <math.h>
+#include <string.h>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace sns;
+
+namespace {
+
+constexpr int64_t kMaxRows = (int64_t(1) << 31) - 1;  // row ids fit 31 bits
+constexpr int64_t kMaxD = 16384;      // CountSketch bucket sort (LDS histograms)
+constexpr int64_t kMaxQrD = 8192;     // register-resident QR panels
+
+sns_status check_matrix(const sns_matrix* A) {
+  if (!A || !A->values) return SNS_ERR_INVALID_ARG;
+  if (A->dtype != SNS_F32 && A->dtype != SNS_F64) return SNS_ERR_DTYPE;
+  if (A->layout != SNS_DENSE_ROWMAJOR && A->layout != SNS_CSR) return SNS_ERR_DTYPE;
+  if (A->m < 1 || A->n < 1 || A->m > kMaxRows) return SNS_ERR_SHAPE;
+  if (A->layout == SNS_DENSE_ROWMAJOR && A->ld < A->n) return SNS_ERR_SHAPE;
+  if (A->layout == SNS_CSR) {
+    if (!A->row_ptr || !A->col_idx) return SNS_ERR_INVALID_ARG;
+    if (A->nnz < 0 || A->nnz > kMaxRows) return SNS_ERR_SHAPE;
+  }
+  return SNS_OK;
+}
+
+sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A) {
+  if (!sk) return SNS_ERR_INVALID_ARG;
+  if (sk->kind != SNS_SKETCH_COUNT && sk->kind != SNS_SKETCH_GAUSSIAN) return SNS_ERR_INVALID_ARG;
+  if (sk->d < 1 || sk->d > kMaxD) return SNS_ERR_SHAPE;
+  if (A) {
+    if (sk->d < A->n || sk->d > A->m) return SNS_ERR_SHAPE;
+    if (sk->kind == SNS_SKETCH_GAUSSIAN && A->dtype != SNS_F32) return SNS_ERR_DTYPE;
+    if (sk->kind == SNS_SKETCH_GAUSSIAN && A->layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+    if (sk->kind == SNS_SKETCH_COUNT && A->layout == SNS_CSR) return SNS_ERR_DTYPE;
+  }
+  return SNS_OK;
+}
+
+size_t elem(const sns_matrix& A) { return A.dtype == SNS_F64 ? 8 : 4; }
+
+// Workspace of the sketch step (sort + partials).
+struct SketchWs {
+  SortPlan sp;
+  GatherPlan gp;
+  SortBufs sb{};
+  void* part = nullptr;
+};
+
+void carve_sketch(Carve& c, const sns_sketch& sk, const sns_matrix& A, bool with_b, bool acc64,
+                  SketchWs& w) {
+  w.sp = make_sort_plan(A.m, (uint32_t)sk.d);
+  w.gp = make_gather_plan(A, (uint32_t)sk.d, acc64);
+  carve_sort(c, w.sp, with_b ? elem(A) : 0, w.sb);
+  const size_t pb = gather_partial_bytes(w.gp, A, (uint32_t)sk.d);
+  w.part = pb ? (void*)c.take<char>(pb) : nullptr;
+}
+
+sns_status run_sketch(const sns_sketch& sk, const sns_matrix& A, const void* b, void* SA, void* Sb,
+                      const SketchWs& w, hipStream_t st) {
+  sns_status s = launch_bucket_sort(w.sp, sk.seed, b, A.dtype, w.sb, st);
+  if (s != SNS_OK) return s;
+  return launch_cs_gather(w.gp, A, (uint32_t)sk.d, w.sb, b != nullptr, SA, Sb, w.part, st);
+}
+
+struct LstsqWs {
+  SketchWs sw;
+  void* SA = nullptr;
+  void* Sb = nullptr;
+  QrBufs q{};
+  LsqrPlan lp;
+  LsqrBufs l{};
+  sns_info* info = nullptr;
+};
+
+void carve_lstsq(Carve& c, const sns_sketch& sk, const sns_matrix& A, const sns_solve_opts& o,
+                 LstsqWs& w) {
+  carve_sketch(c, sk, A, true, o.accum_fp64 != 0, w.sw);
+  w.SA = c.take<char>((size_t)sk.d * A.n * elem(A));
+  w.Sb = c.take<char>((size_t)sk.d * elem(A));
+  carve_qr(c, sk.d, A.n, w.q);
+  if (o.refine) {
+    w.lp = make_lsqr_plan(A);
+    carve_lsqr(c, A, w.lp, w.l);
+  }
+  w.info = c.take<sns_info>(1);
+}
+
+sns_solve_opts default_opts() {
+  sns_solve_opts o;
+  o.refine = 0;
+  o.max_iters = 0;
+  o.rtol = 0.0;
+  o.accum_fp64 = 0;
+  return o;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sns_status_string(int status) {
+  switch (status) {
+    case SNS_OK: return "SNS_OK";
+    case SNS_ERR_INVALID_ARG: return "SNS_ERR_INVALID_ARG";
+    case SNS_ERR_SHAPE: return "SNS_ERR_SHAPE";
+    case SNS_ERR_DTYPE: return "SNS_ERR_DTYPE";
+    case SNS_ERR_RANK_DEFICIENT: return "SNS_ERR_RANK_DEFICIENT";
+    case SNS_ERR_NOT_CONVERGED: return "SNS_ERR_NOT_CONVERGED";
+    case SNS_ERR_NUMERICAL: return "SNS_ERR_NUMERICAL";
+    case SNS_ERR_OUT_OF_MEMORY: return "SNS_ERR_OUT_OF_MEMORY";
+    case SNS_ERR_QUEUE_FULL: return "SNS_ERR_QUEUE_FULL";
+    case SNS_ERR_NOT_READY: return "SNS_ERR_NOT_READY";
+    case SNS_ERR_HIP: return "SNS_ERR_HIP";
+    default: return "SNS_ERR_UNKNOWN";
+  }
+}
+
+int sns_version(void) { return 100; }
+
+sns_status sns_hash(uint64_t seed, int64_t d, int64_t i0, int64_t count, uint32_t* h, int8_t* s,
+                    void* stream) {
+  if (d < 1 || d > 0xFFFFFFFFll || count < 0 || i0 < 0) return SNS_ERR_SHAPE;
+  if (count > 0 && !h && !s) return SNS_ERR_INVALID_ARG;
+  return launch_hash(seed, (uint32_t)d, i0, count, h, s, (hipStream_t)stream);
+}
+
+sns_status sns_sketch_workspace_size(const sns_sketch* sk, const sns_matrix* A, size_t* bytes) {
+  sns_status s = check_matrix(A);
+  if (s != SNS_OK) return s;
+  if ((s = check_sketch(sk, A)) != SNS_OK) return s;
+  if (!bytes) return SNS_ERR_INVALID_ARG;
+  if (sk->kind == SNS_SKETCH_GAUSSIAN) {
+    *bytes = gauss_workspace_bytes(*A, (uint32_t)sk->d);
+    return SNS_OK;
+  }
+  Carve c(nullptr, 0);
+  SketchWs w;
+  carve_sketch(c, *sk, *A, true, true, w);
+  *bytes = c.off;
+  return SNS_OK;
+}
+
+sns_status sns_sketch_apply(const sns_sketch* sk, const sns_matrix* A, const void* b, void* SA,
+                            void* Sb, const sns_solve_opts* opts, void* workspace, size_t ws_bytes,
+                            void* stream) {
+  sns_status s = check_matrix(A);
+  if (s != SNS_OK) return s;
+  if ((s = check_sketch(sk, A)) != SNS_OK) return s;
+  if (!SA || !workspace) return SNS_ERR_INVALID_ARG;
+  if ((b == nullptr) != (Sb == nullptr)) return SNS_ERR_INVALID_ARG;
+  const bool acc64 = opts && opts->accum_fp64;
+  hipStream_t st = (hipStream_t)stream;
+  if (sk->kind == SNS_SKETCH_GAUSSIAN) {
+    if (ws_bytes < gauss_workspace_bytes(*A, (uint32_t)sk->d)) return SNS_ERR_OUT_OF_MEMORY;
+    return launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, SA, Sb, workspace, st);
+  }
+  Carve c(workspace, ws_bytes);
+  SketchWs w;
+  carve_sketch(c, *sk, *A, b != nullptr, acc64, w);
+  if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
+  return run_sketch(*sk, *A, b, SA, Sb, w, st);
+}
+
+sns_status sns_qr_solve_workspace_size(int64_t d, int64_t n, size_t* bytes) {
+  if (!bytes) return SNS_ERR_INVALID_ARG;
+  if (n < 1 || d < n || d > kMaxQrD || n > 4096) return SNS_ERR_SHAPE;
+  *bytes = qr_workspace_bytes(d, n) + align_up(sizeof(sns_info));
+  return SNS_OK;
+}
+
+sns_status sns_qr_solve(int64_t d, int64_t n, sns_dtype dtype, const void* SA, int64_t ld_sa,
+                        const void* Sb, double* x0, double* R, sns_info* info, void* workspace,
+                        size_t ws_bytes, void* stream) {
+  if (!SA || !Sb || !x0 || !workspace) return SNS_ERR_INVALID_ARG;
+  if (dtype != SNS_F32 && dtype != SNS_F64) return SNS_ERR_DTYPE;
+  if (n < 1 || d < n || d > kMaxQrD || n > 4096 || ld_sa < n) return SNS_ERR_SHAPE;
+  Carve c(workspace, ws_bytes);
+  QrBufs q;
+  carve_qr(c, d, n, q);
+  sns_info* idev = c.take<sns_info>(1);
+  if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
+  hipStream_t st = (hipStream_t)stream;
+  sns_status s = launch_qr_solve(d, n, dtype, SA, ld_sa, Sb, q, x0, R, idev, st);
+  if (s != SNS_OK) return s;
+  if (info) SNS_HIP_TRY(hipMemcpyAsync(info, idev, sizeof(sns_info), hipMemcpyDeviceToHost, st));
+  return SNS_OK;
+}
+
+sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
+                                    const sns_solve_opts* opts, size_t* bytes) {
+  sns_status s = check_matrix(A);
+  if (s != SNS_OK) return s;
+  if ((s = check_sketch(sk, A)) != SNS_OK) return s;
+  if (!bytes) return SNS_ERR_INVALID_ARG;
+  const sns_solve_opts o = opts ? *opts : default_opts();
+  Carve c(nullptr, 0);
+  LstsqWs w;
+  carve_lstsq(c, *sk, *A, o, w);
+  size_t extra = sk->kind == SNS_SKETCH_GAUSSIAN ? gauss_workspace_bytes(*A, (uint32_t)sk->d) : 0;
+  *bytes = c.off + align_up(extra);
+  return SNS_OK;
+}
+
+sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, double* x,
+                     const sns_solve_opts* opts, void* workspace, size_t ws_bytes, sns_info* info,
+                     void* stream) {
+  sns_status s = check_matrix(A);
+  if (s != SNS_OK) return s;
+  if ((s = check_sketch(sk, A)) != SNS_OK) return s;
+  if (!b || !x || !workspace) return SNS_ERR_INVALID_ARG;
+  const sns_solve_opts o = opts ? *opts : default_opts();
+  if (o.refine && (o.max_iters < 0 || !(o.rtol >= 0.0))) return SNS_ERR_INVALID_ARG;
+  if (A->n > 4096 || sk->d > kMaxQrD) return SNS_ERR_SHAPE;
+  if (o.refine && A->n > 2048) return SNS_ERR_SHAPE;
+  if (o.refine && (((uintptr_t)A->values % 16) != 0 || (A->ld * elem(*A)) % 16 != 0))
+    return SNS_ERR_SHAPE;
+  Carve c(workspace, ws_bytes);
+  LstsqWs w;
+  carve_lstsq(c, *sk, *A, o, w);
+  void* gws = nullptr;
+  if (sk->kind == SNS_SKETCH_GAUSSIAN) gws = c.take<char>(gauss_workspace_bytes(*A, (uint32_t)sk->d));
+  if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
+  hipStream_t st = (hipStream_t)stream;
+  if (sk->kind == SNS_SKETCH_GAUSSIAN)
+    s = launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, gws, st);
+  else
+    s = run_sketch(*sk, *A, b, w.SA, w.Sb, w.sw, st);
+  if (s != SNS_OK) return s;
+  s = launch_qr_solve(sk->d, A->n, A->dtype, w.SA, A->n, w.Sb, w.q, w.q.xw, nullptr, w.info, st);
+  if (s != SNS_OK) return s;
+  if (o.refine) {
+    s = launch_sap_refine(*A, b, w.lp, w.l, w.q, (int)sk->d, o.max_iters, o.rtol, x, w.info, st);
+    if (s != SNS_OK) return s;
+  } else {
+    SNS_HIP_TRY(hipMemcpyAsync(x, w.q.xw, sizeof(double) * A->n, hipMemcpyDeviceToDevice, st));
+  }
+  if (info) SNS_HIP_TRY(hipMemcpyAsync(info, w.info, sizeof(sns_info), hipMemcpyDeviceToHost, st));
+  return SNS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,212 @@
+// Stable counting sort of rows by CountSketch bucket (deterministic, integer
+// only).  Rows are cut into wave-blocks of `rw` consecutive rows; each wave
+// histograms its block in LDS, a two-level exclusive scan in bucket-major
+// order turns the per-block counts into start offsets, and each wave then
+// places its rows in ascending order, ranking equal buckets within a batch of
+// 64 rows by lane order.  The resulting order inside a bucket is ascending row
+// index, independent of the launch.
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sns {
+
+namespace {
+
+// Row hashes for the test entry point.
+__global__ void k_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uint32_t* h,
+                       int8_t* s) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const Hash r = cs_hash(seed, d, (uint64_t)(i0 + t));
+    if (h) h[t] = r.h;
+    if (s) s[t] = r.neg ? -1 : 1;
+  }
+}
+
+// counts[wb * d + k] = number of rows of wave-block wb in bucket k.
+__global__ void k_sort_count(uint64_t seed, uint32_t d, int64_t m, int64_t rw, int64_t nwb,
+                             uint32_t* __restrict__ counts) {
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t wb = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  uint32_t* hist = lds + (size_t)wv * d;
+  for (uint32_t k = lane; k < d; k += 64) hist[k] = 0u;
+  __syncthreads();
+  if (wb < nwb) {
+    const int64_t r0 = wb * rw, r1 = min(m, r0 + rw);  // r0 is even
+    for (int64_t j = (r0 >> 1) + lane; 2 * j < r1; j += 64) {
+      Hash e, o;
+      cs_hash_pair(seed, d, (uint64_t)j, e, o);
+      atomicAdd(&hist[e.h], 1u);
+      if (2 * j + 1 < r1) atomicAdd(&hist[o.h], 1u);
+    }
+  }
+  __syncthreads();
+  if (wb < nwb)
+    for (uint32_t k = lane; k < d; k += 64) counts[wb * d + k] = hist[k];
+}
+
+// Within each segment of `seg` wave-blocks, replace counts by their exclusive
+// prefix (per bucket) and record the segment totals.
+__global__ void k_scan_segments(uint32_t d, int64_t nwb, int64_t seg, uint32_t* __restrict__ counts,
+                                uint32_t* __restrict__ segtot) {
+  const uint32_t k = blockIdx.x * 64 + threadIdx.x;
+  const int64_t s = blockIdx.y;
+  if (k >= d) return;
+  const int64_t w0 = s * seg, w1 = min(nwb, w0 + seg);
+  uint32_t run = 0;
+  for (int64_t wb = w0; wb < w1; ++wb) {
+    const uint32_t c = counts[wb * d + k];
+    counts[wb * d + k] = run;
+    run += c;
+  }
+  segtot[s * d + k] = run;
+}
+
+// Exclusive scan across segments per bucket (in place in segtot), then across
+// buckets: bucket_ptr[k] = rows in buckets < k, bucket_ptr[d] = m.
+__global__ void k_scan_buckets(uint32_t d, int64_t nseg, uint32_t* __restrict__ segtot,
+                               uint32_t* __restrict__ bucket_ptr) {
+  __shared__ uint32_t wsum[16];
+  const int t = threadIdx.x, nt = blockDim.x;  // 1024 threads
+  const uint32_t per = (d + nt - 1) / nt;
+  const uint32_t k0 = min(d, t * per), k1 = min(d, k0 + per);
+  uint32_t local = 0;
+  for (uint32_t k = k0; k < k1; ++k) {
+    uint32_t run = 0;
+    for (int64_t s = 0; s < nseg; ++s) {
+      const uint32_t c = segtot[s * d + k];
+      segtot[s * d + k] = run;
+      run += c;
+    }
+    bucket_ptr[k] = run;  // bucket total for now
+    local += run;
+  }
+  // exclusive scan of `local` over threads
+  const int lane = t & 63, wv = t >> 6;
+  uint32_t incl = local;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += y;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wv; ++w) before += wsum[w];
+  uint32_t run = before + incl - local;
+  for (uint32_t k = k0; k < k1; ++k) {
+    const uint32_t c = bucket_ptr[k];
+    bucket_ptr[k] = run;
+    run += c;
+  }
+  if (t == nt - 1) bucket_ptr[d] = run;
+}
+
+template <typename BT>
+__global__ void k_sort_scatter(uint64_t seed, uint32_t d, int64_t m, int64_t rw, int64_t nwb,
+                               int64_t seg, const uint32_t* __restrict__ counts,
+                               const uint32_t* __restrict__ segtot,
+                               const uint32_t* __restrict__ bucket_ptr, const BT* __restrict__ b,
+                               uint32_t* __restrict__ perm, BT* __restrict__ bperm) {
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t wb = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  uint32_t* next = lds + (size_t)wv * d;
+  if (wb < nwb) {
+    const int64_t s = wb / seg;
+    for (uint32_t k = lane; k < d; k += 64)
+      next[k] = bucket_ptr[k] + segtot[s * d + k] + counts[wb * d + k];
+  }
+  __syncthreads();
+  if (wb >= nwb) return;
+  const int64_t r0 = wb * rw, r1 = min(m, r0 + rw);
+  for (int64_t r = r0; r < r1; r += 64) {
+    const int64_t i = r + lane;
+    const bool valid = i < r1;
+    const Hash hs = cs_hash(seed, d, (uint64_t)i);
+    const uint32_t h = valid ? hs.h : 0xFFFFFFFFu;
+    // rank among the earlier lanes of this batch with the same bucket
+    uint32_t rank = 0;
+    bool last = true;
+#pragma unroll 8
+    for (int q = 0; q < 64; ++q) {
+      const uint32_t hq = __shfl(h, q, 64);
+      if (hq == h) {
+        if (q < lane) ++rank;
+        if (q > lane) last = false;
+      }
+    }
+    if (valid) {
+      const uint32_t pos = next[h] + rank;
+      perm[pos] = (uint32_t)i | (hs.neg ? 0x80000000u : 0u);
+      if (bperm) {
+        const BT v = b[i];
+        bperm[pos] = hs.neg ? -v : v;
+      }
+      if (last) next[h] = pos + 1;
+    }
+  }
+}
+
+}  // namespace
+
+SortPlan make_sort_plan(int64_t m, uint32_t d) {
+  SortPlan p;
+  p.m = m;
+  p.d = d;
+  int64_t rw = (m + 4095) / 4096;
+  rw = (rw + 63) / 64 * 64;
+  p.rw = rw < 512 ? 512 : rw;
+  p.nwb = (m + p.rw - 1) / p.rw;
+  int w = (int)(16384 / d);
+  p.waves = w < 1 ? 1 : (w > 4 ? 4 : w);
+  p.seg = 64;
+  p.nseg = (p.nwb + p.seg - 1) / p.seg;
+  return p;
+}
+
+void carve_sort(Carve& c, const SortPlan& p, size_t b_elem_bytes, SortBufs& s) {
+  s.perm = c.take<uint32_t>((size_t)p.m);
+  s.bperm = b_elem_bytes ? (void*)c.take<char>((size_t)p.m * b_elem_bytes) : nullptr;
+  s.bucket_ptr = c.take<uint32_t>((size_t)p.d + 1);
+  s.counts = c.take<uint32_t>((size_t)p.d * p.nwb);
+  s.segtot = c.take<uint32_t>((size_t)p.d * p.nseg);
+}
+
+sns_status launch_bucket_sort(const SortPlan& p, uint64_t seed, const void* b, sns_dtype bt,
+                              const SortBufs& s, hipStream_t st) {
+  const int nthr = p.waves * 64;
+  const unsigned nblk = (unsigned)((p.nwb + p.waves - 1) / p.waves);
+  const size_t lds = (size_t)p.waves * p.d * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_sort_count, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m, p.rw, p.nwb,
+                     s.counts);
+  hipLaunchKernelGGL(k_scan_segments, dim3((p.d + 63) / 64, (unsigned)p.nseg), dim3(64), 0, st,
+                     p.d, p.nwb, p.seg, s.counts, s.segtot);
+  hipLaunchKernelGGL(k_scan_buckets, dim3(1), dim3(1024), 0, st, p.d, p.nseg, s.segtot,
+                     s.bucket_ptr);
+  if (bt == SNS_F64 || !b) {
+    hipLaunchKernelGGL(k_sort_scatter<double>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
+                       p.rw, p.nwb, p.seg, s.counts, s.segtot, s.bucket_ptr,
+                       static_cast<const double*>(b), s.perm,
+                       b ? static_cast<double*>(s.bperm) : nullptr);
+  } else {
+    hipLaunchKernelGGL(k_sort_scatter<float>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
+                       p.rw, p.nwb, p.seg, s.counts, s.segtot, s.bucket_ptr,
+                       static_cast<const float*>(b), s.perm, static_cast<float*>(s.bperm));
+  }
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
+}
+
+sns_status launch_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uint32_t* h,
+                       int8_t* s, hipStream_t st) {
+  if (count == 0) return SNS_OK;
+  int64_t blocks = (count + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_hash, dim3((unsigned)blocks), dim3(256), 0, st, seed, d, i0, count, h, s);
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
+}
+
+}  // namespace sns

@@ -1,0 +1,82 @@
+"""The C ABI library loads, exports every symbol include/sns.h declares, and
+rejects bad arguments on the host (no device work is enqueued for them)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sns.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sns_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    import paper_2409_14309_amd as sns
+    lib = sns.load()
+    decl = _declared()
+    assert "sns_lstsq" in decl and "sns_sketch_apply" in decl
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) <= set(sns.exported_symbols())
+
+
+def test_status_strings_and_version():
+    import paper_2409_14309_amd as sns
+    assert sns.sns_status_string(0) == "SNS_OK"
+    assert sns.sns_status_string(4) == "SNS_ERR_RANK_DEFICIENT"
+    assert sns.sns_version() >= 100
+
+
+def test_host_side_argument_checks():
+    import paper_2409_14309_amd as sns
+    lib = sns.load()
+    nb = C.c_size_t()
+    sk = sns.Sketch(0, 64, 1)
+    fake = 0x1000  # never dereferenced: every call below fails validation first
+    cases = [
+        (sns.Matrix(1000, 0, 0, 0, fake, 0, None, None, 0), sk, 2),       # n = 0
+        (sns.Matrix(1000, 100, 0, 0, fake, 100, None, None, 0), sk, 2),   # d < n
+        (sns.Matrix(50, 10, 0, 0, fake, 10, None, None, 0), sk, 2),       # m < d
+        (sns.Matrix(1000, 10, 0, 0, fake, 5, None, None, 0), sk, 2),      # ld < n
+        (sns.Matrix(1000, 10, 7, 0, fake, 10, None, None, 0), sk, 3),     # bad dtype
+        (sns.Matrix(1000, 10, 0, 0, None, 10, None, None, 0), sk, 1),     # null values
+        (sns.Matrix(1000, 10, 1, 0, fake, 10, None, None, 0), sns.Sketch(1, 64, 1), 3),  # gaussian f64
+        (sns.Matrix(1000, 10, 0, 0, fake, 10, None, None, 0), sns.Sketch(5, 64, 1), 1),  # bad kind
+    ]
+    for A, s, want in cases:
+        assert lib.sns_sketch_workspace_size(C.byref(s), C.byref(A), C.byref(nb)) == want
+        assert lib.sns_sketch_apply(C.byref(s), C.byref(A), None, C.c_void_p(fake), None, None,
+                                    C.c_void_p(fake), 1 << 30, None) == want
+    A = sns.Matrix(1000, 10, 0, 0, fake, 10, None, None, 0)
+    assert lib.sns_sketch_workspace_size(C.byref(sk), C.byref(A), C.byref(nb)) == 0 and nb.value > 0
+    # b without Sb
+    assert lib.sns_sketch_apply(C.byref(sk), C.byref(A), C.c_void_p(fake), C.c_void_p(fake), None,
+                                None, C.c_void_p(fake), 1 << 30, None) == 1
+    # workspace too small
+    assert lib.sns_sketch_apply(C.byref(sk), C.byref(A), None, C.c_void_p(fake), None, None,
+                                C.c_void_p(fake), 16, None) == 7
+    o = sns.opts(refine=1, max_iters=-1)
+    assert lib.sns_lstsq(C.byref(sk), C.byref(A), C.c_void_p(fake), C.c_void_p(fake), C.byref(o),
+                         C.c_void_p(fake), 1 << 30, None, None) == 1
+    assert lib.sns_qr_solve(10, 20, 0, C.c_void_p(fake), 20, C.c_void_p(fake), C.c_void_p(fake),
+                            None, None, C.c_void_p(fake), 1 << 30, None) == 2
+    assert lib.sns_hash(1, 0, 0, 10, C.c_void_p(fake), None, None) == 2
+
+
+def test_device_gaussian_table_matches_oracle_bits():
+    """The library builds its own table (host inverse normal + bf16 rounding);
+    it must equal the oracle's table bit for bit."""
+    import struct
+
+    import paper_2409_14309_amd as sns
+    from oracle.sketch import gaussian_table
+    got = sns.sns_gaussian_table()
+    ref = np.array([struct.unpack("<I", struct.pack("<f", np.float32(v)))[0] >> 16
+                    for v in gaussian_table()], dtype=np.uint16)
+    assert np.array_equal(got, ref)

@@ -1,0 +1,144 @@
+"""GPU parity of the QR solve (Sec. 1.2 step 3) and of sns_lstsq (SAS and
+SAP-SAS, Secs. 1.2, 1.3, 2.1) against the oracle.
+
+Bars: fp64 R and x0 from the same SA agree to 1e-12 relative (the LAPACK sign
+convention is shared, so R is compared entry by entry); the plain fp64 solve
+of the 20000 x 50 workload agrees to 1e-12; fp64 refinement with a fixed
+iteration count agrees to 1e-9 (kappa(R) ~ 1e3 amplifies rounding); fp32
+refinement on a well-conditioned problem agrees to 1e-5 in forward error;
+on the ill-conditioned fp32 problem (kappa 1e6) the criterion is the residual
+error RE <= 1e-6 against the fp64 least-squares solution, reached by the
+device stop rule.
+"""
+import numpy as np
+import pytest
+
+from oracle import metrics as OM
+from oracle import qr as OQ
+from oracle import solve as OSV
+from workloads import dense_gaussian, dense_ill_conditioned
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x, torch):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _qr_gpu(sns, torch, SA, Sb):
+    d, n = SA.shape
+    ws = torch.empty(sns.sns_qr_solve_workspace_size(d, n), dtype=torch.uint8, device="cuda")
+    x0 = torch.empty(n, dtype=torch.float64, device="cuda")
+    R = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    info = sns.Info()
+    sns.sns_qr_solve(d, n, _dev(SA, torch), _dev(Sb, torch), x0, R, ws, info)
+    torch.cuda.synchronize()
+    return x0.cpu().numpy(), R.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("d,n", [(200, 50), (1024, 256), (600, 600), (2100, 130), (80, 1),
+                                 (513, 17), (4000, 97)])
+def test_qr_solve_matches_oracle(gpu_lib, d, n):
+    import torch
+    rng = np.random.default_rng(d * 7 + n)
+    SA = rng.standard_normal((d, n))
+    Sb = rng.standard_normal(d)
+    x0, R, info = _qr_gpu(gpu_lib, torch, SA, Sb)
+    Rr, c, rho, _, _ = OQ.householder_qr_augmented(SA, Sb)
+    xr = OQ.back_substitution(Rr, c)
+    assert info.status == 0
+    assert np.linalg.norm(R - Rr) <= 1e-12 * np.linalg.norm(Rr)
+    assert np.linalg.norm(x0 - xr) <= 1e-12 * np.linalg.norm(xr) * max(1.0, np.linalg.cond(Rr) / 1e3)
+    assert abs(info.sketch_resid - rho) <= 1e-12 * max(rho, 1.0)
+
+
+def test_qr_solve_fp32_input_and_rank_deficiency(gpu_lib):
+    import torch
+    rng = np.random.default_rng(11)
+    SA = rng.standard_normal((300, 40)).astype(np.float32)
+    Sb = rng.standard_normal(300).astype(np.float32)
+    x0, R, info = _qr_gpu(gpu_lib, torch, SA, Sb)
+    Rr, c, rho, _, _ = OQ.householder_qr_augmented(SA.astype(np.float64), Sb.astype(np.float64))
+    assert np.linalg.norm(R - Rr) <= 1e-12 * np.linalg.norm(Rr)
+    SA = rng.standard_normal((300, 40))
+    SA[:, 7] = SA[:, 3]
+    _, _, info = _qr_gpu(gpu_lib, torch, SA, rng.standard_normal(300))
+    assert info.status == 4  # SNS_ERR_RANK_DEFICIENT
+
+
+def test_plain_fp64_20000x50(gpu_lib):
+    """The plain FP64 sketch-and-solve workload at full size."""
+    import torch
+    sns = gpu_lib
+    p = dense_gaussian(20000, 50, seed=1000)
+    x, info = sns.lstsq(_dev(p.A, torch), _dev(p.b, torch), "count", 200, 42)
+    r = OSV.sketch_and_solve(p.A, p.b, "count", 42, 200)
+    xg = x.cpu().numpy()
+    assert info.status == 0 and info.iters == 0
+    assert np.linalg.norm(xg - r.x) <= 1e-12 * np.linalg.norm(r.x)
+    assert abs(info.sketch_resid - r.rho) <= 1e-12 * r.rho
+    # accuracy of the method itself (reported, not a parity bar)
+    xs = OM.lstsq_exact(p.A, p.b)
+    fe = np.linalg.norm(xg - xs) / np.linalg.norm(xs)
+    assert fe < 1e-3
+
+
+def test_refine_fp64_fixed_iterations(gpu_lib):
+    import torch
+    sns = gpu_lib
+    p = dense_ill_conditioned(30000, 40, seed=21, cond=1e3, dtype=np.float64)
+    for k in (1, 3, 8):
+        x, info = sns.lstsq(_dev(p.A, torch), _dev(p.b, torch), "count", 160, 42, refine=True,
+                            max_iters=k, rtol=0.0)
+        r = OSV.sap_sas(p.A, p.b, "count", 42, 160, k)
+        assert info.iters == k
+        xg = x.cpu().numpy()
+        assert np.linalg.norm(xg - r.x) <= 1e-9 * np.linalg.norm(r.x), k
+
+
+def test_refine_fp32_well_conditioned_fixed_iterations(gpu_lib):
+    import torch
+    sns = gpu_lib
+    p = dense_gaussian(50000, 64, seed=22, dtype=np.float32)
+    x, info = sns.lstsq(_dev(p.A, torch), _dev(p.b, torch), "count", 256, 42, refine=True,
+                        max_iters=3, rtol=0.0)
+    r = OSV.sap_sas(p.A, p.b, "count", 42, 256, 3)
+    xg = x.cpu().numpy()
+    assert info.iters == 3
+    assert np.linalg.norm(xg - r.x) <= 1e-5 * np.linalg.norm(r.x)
+
+
+@pytest.mark.parametrize("m,n,d", [(1 << 17, 64, 256), (200000, 100, 400)])
+def test_refine_fp32_illconditioned_stop_rule(gpu_lib, m, n, d):
+    import torch
+    sns = gpu_lib
+    p = dense_ill_conditioned(m, n, seed=23, cond=1e6)
+    x, info = sns.lstsq(_dev(p.A, torch), _dev(p.b, torch), "count", d, 42, refine=True,
+                        max_iters=100, rtol=1e-6)
+    assert info.status == 0
+    xs = OM.lstsq_exact(p.A, p.b)
+    met = OM.metrics(p.A, p.b, x.cpu().numpy(), xs)
+    assert met["RE"] <= 1e-6, met
+    r = OSV.sap_sas(p.A, p.b, "count", 42, d, 100, rtol=1e-6)
+    assert abs(info.iters - r.iters) <= 2
+    assert info.rel_resid_est <= 1e-6
+
+
+def test_refine_zero_iterations_returns_sketch_solution(gpu_lib):
+    import torch
+    sns = gpu_lib
+    p = dense_gaussian(8000, 20, seed=24)
+    x0, _ = sns.lstsq(_dev(p.A, torch), _dev(p.b, torch), "count", 80, 3)
+    x1, info = sns.lstsq(_dev(p.A, torch), _dev(p.b, torch), "count", 80, 3, refine=True,
+                         max_iters=0, rtol=0.0)
+    assert info.iters == 0
+    assert np.array_equal(x0.cpu().numpy(), x1.cpu().numpy())
+
+
+def test_exact_recovery(gpu_lib):
+    import torch
+    sns = gpu_lib
+    p = dense_gaussian(10000, 30, seed=25)
+    b = p.A @ p.x_true
+    x, info = sns.lstsq(_dev(p.A, torch), _dev(b, torch), "count", 120, 9)
+    assert np.linalg.norm(x.cpu().numpy() - p.x_true) <= 1e-11 * np.linalg.norm(p.x_true)
