@@ -175,6 +175,18 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
                      const sns_solve_opts* opts, void* workspace, size_t ws_bytes,
                      sns_info* info, void* stream);
 
+/* Kernel timing (tracing support).  While enabled, every kernel the library
+ * launches is bracketed by two HIP events on its stream; sns_timing_summary
+ * waits for the recorded launches and writes one line per kernel name,
+ * "name launches total_ms avg_us", after a header line, into buf (host, len
+ * bytes, truncated and NUL-terminated), returning the untruncated length.
+ * SNS_TRACE=1 in the environment enables timing at the first call and prints
+ * the summary to stderr at exit.  Not for use while another thread launches
+ * library work. */
+void sns_timing_enable(int on);
+void sns_timing_reset(void);
+int sns_timing_summary(char* buf, size_t len);
+
 #ifdef __cplusplus
 }
 #endif

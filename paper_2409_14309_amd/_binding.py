@@ -70,6 +70,9 @@ _SIGS = {
     "sns_lstsq": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix), C.c_void_p, C.c_void_p,
                             C.POINTER(SolveOpts), C.c_void_p, C.c_size_t, C.POINTER(Info),
                             C.c_void_p]),
+    "sns_timing_enable": (None, [C.c_int]),
+    "sns_timing_reset": (None, []),
+    "sns_timing_summary": (C.c_int, [C.c_char_p, C.c_size_t]),
 }
 
 
@@ -209,3 +212,28 @@ def sns_lstsq(sk: Sketch, A: Matrix, b, x, opt: SolveOpts, workspace, info: Info
                             _ptr(workspace), workspace.numel() * workspace.element_size(),
                             C.byref(info) if info is not None else None, _stream(stream)),
            "sns_lstsq")
+
+
+# ------------------------------------------------------------- timing ----
+
+def sns_timing_enable(on: bool = True):
+    load().sns_timing_enable(1 if on else 0)
+
+
+def sns_timing_reset():
+    load().sns_timing_reset()
+
+
+def sns_timing_summary() -> dict:
+    """{kernel: (launches, total_ms, avg_us)} of the launches timed so far."""
+    lib = load()
+    need = lib.sns_timing_summary(None, 0)
+    buf = C.create_string_buffer(need + 1)
+    lib.sns_timing_summary(buf, need + 1)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        if not line or line.startswith("#"):
+            continue
+        name, cnt, tot, avg = line.split()
+        out[name] = (int(cnt), float(tot), float(avg))
+    return out

@@ -179,19 +179,19 @@ sns_status launch_bucket_sort(const SortPlan& p, uint64_t seed, const void* b, s
   const int nthr = p.waves * 64;
   const unsigned nblk = (unsigned)((p.nwb + p.waves - 1) / p.waves);
   const size_t lds = (size_t)p.waves * p.d * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_sort_count, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m, p.rw, p.nwb,
+  SNS_LAUNCH("sort_count", k_sort_count, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m, p.rw, p.nwb,
                      s.counts);
-  hipLaunchKernelGGL(k_scan_segments, dim3((p.d + 63) / 64, (unsigned)p.nseg), dim3(64), 0, st,
+  SNS_LAUNCH("scan_segments", k_scan_segments, dim3((p.d + 63) / 64, (unsigned)p.nseg), dim3(64), 0, st,
                      p.d, p.nwb, p.seg, s.counts, s.segtot);
-  hipLaunchKernelGGL(k_scan_buckets, dim3(1), dim3(1024), 0, st, p.d, p.nseg, s.segtot,
+  SNS_LAUNCH("scan_buckets", k_scan_buckets, dim3(1), dim3(1024), 0, st, p.d, p.nseg, s.segtot,
                      s.bucket_ptr);
   if (bt == SNS_F64 || !b) {
-    hipLaunchKernelGGL(k_sort_scatter<double>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
+    SNS_LAUNCH("sort_scatter", k_sort_scatter<double>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
                        p.rw, p.nwb, p.seg, s.counts, s.segtot, s.bucket_ptr,
                        static_cast<const double*>(b), s.perm,
                        b ? static_cast<double*>(s.bperm) : nullptr);
   } else {
-    hipLaunchKernelGGL(k_sort_scatter<float>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
+    SNS_LAUNCH("sort_scatter", k_sort_scatter<float>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
                        p.rw, p.nwb, p.seg, s.counts, s.segtot, s.bucket_ptr,
                        static_cast<const float*>(b), s.perm, static_cast<float*>(s.bperm));
   }
@@ -204,7 +204,7 @@ sns_status launch_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uin
   if (count == 0) return SNS_OK;
   int64_t blocks = (count + 255) / 256;
   if (blocks > 8192) blocks = 8192;
-  hipLaunchKernelGGL(k_hash, dim3((unsigned)blocks), dim3(256), 0, st, seed, d, i0, count, h, s);
+  SNS_LAUNCH("hash", k_hash, dim3((unsigned)blocks), dim3(256), 0, st, seed, d, i0, count, h, s);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }

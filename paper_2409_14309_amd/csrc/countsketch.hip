@@ -149,7 +149,7 @@ void launch_one(const GatherPlan& g, const sns_matrix& A, uint32_t d, const Sort
   const dim3 grid(d * g.nseg, g.coltiles);
   Acc* pa = g.nseg > 1 ? static_cast<Acc*>(part) : nullptr;
   Acc* pb = (g.nseg > 1 && with_b) ? pa + (size_t)g.nseg * d * A.n : nullptr;
-  hipLaunchKernelGGL((k_cs_gather<T, Acc, VEC, LPR, kWaves, kUnroll>), grid, dim3(kWaves * 64), 0,
+  SNS_LAUNCH("cs_gather", (k_cs_gather<T, Acc, VEC, LPR, kWaves, kUnroll>), grid, dim3(kWaves * 64), 0,
                      st, static_cast<const T*>(A.values), A.ld, (int)A.n, s.perm,
                      with_b ? static_cast<const T*>(s.bperm) : nullptr, s.bucket_ptr, d, g.nseg,
                      static_cast<T*>(SA), static_cast<T*>(Sb), pa, pb);
@@ -157,7 +157,7 @@ void launch_one(const GatherPlan& g, const sns_matrix& A, uint32_t d, const Sort
     const int64_t dn = (int64_t)d * A.n;
     int64_t blocks = (dn + d + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL((k_seg_reduce<T, Acc>), dim3((unsigned)blocks), dim3(256), 0, st, dn,
+    SNS_LAUNCH("seg_reduce", (k_seg_reduce<T, Acc>), dim3((unsigned)blocks), dim3(256), 0, st, dn,
                        (int64_t)d, g.nseg, pa, pb, static_cast<T*>(SA),
                        with_b ? static_cast<T*>(Sb) : nullptr);
   }

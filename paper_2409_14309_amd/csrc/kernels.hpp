@@ -9,6 +9,17 @@
 
 namespace sns {
 
+// Kernel timing hooks (no-ops unless timing is enabled).
+void timing_begin(const char* name, hipStream_t s);
+void timing_end(hipStream_t s);
+
+#define SNS_LAUNCH(name, kernel, grid, block, lds, stream, ...)              \
+  do {                                                                      \
+    ::sns::timing_begin(name, stream);                                      \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);      \
+    ::sns::timing_end(stream);                                              \
+  } while (0)
+
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // Bump allocator over a caller-provided workspace.

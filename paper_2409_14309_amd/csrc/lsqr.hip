@@ -312,7 +312,7 @@ template <typename T, int VEC, int LPR, int NCH>
 void launch_pass_t(const sns_matrix& A, const LsqrPlan& p, const LsqrBufs& l, const void* uin,
                    hipStream_t s) {
   double* vecs = l.vecs;
-  hipLaunchKernelGGL((k_lsqr_pass<T, VEC, LPR, NCH>), dim3(p.grid), dim3(kPassWaves * 64), 0, s,
+  SNS_LAUNCH("lsqr_pass", (k_lsqr_pass<T, VEC, LPR, NCH>), dim3(p.grid), dim3(kPassWaves * 64), 0, s,
                      static_cast<const T*>(A.values), A.ld, A.m, (int)A.n,
                      static_cast<const LsqrState*>(l.state), vecs, static_cast<const T*>(uin),
                      static_cast<T*>(l.u), l.zpart, l.npart);
@@ -374,6 +374,32 @@ void carve_lsqr(Carve& c, const sns_matrix& A, const LsqrPlan& p, LsqrBufs& l) {
   l.state = c.take<LsqrState>(1);
 }
 
+namespace {
+
+// Host-side view of the device stop state, copied after every LSQR step into
+// pinned memory so the host can decide how far ahead to enqueue.
+struct PollRing {
+  static constexpr int kSlots = 8;
+  LsqrState* slot = nullptr;  // pinned host memory
+  hipEvent_t ev[kSlots] = {};
+  bool ok = false;
+  PollRing() {
+    if (hipHostMalloc((void**)&slot, sizeof(LsqrState) * kSlots, hipHostMallocDefault) !=
+        hipSuccess)
+      return;
+    for (int i = 0; i < kSlots; ++i)
+      if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) return;
+    ok = true;
+  }
+};
+
+PollRing& poll_ring() {
+  thread_local PollRing r;
+  return r;
+}
+
+}  // namespace
+
 sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan& p,
                              const LsqrBufs& l, const QrBufs& q, int d, int max_iters,
                              double rtol, double* x, sns_info* info_dev, hipStream_t s) {
@@ -388,19 +414,79 @@ sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan&
   double* wd = l.vecs + 2 * n;
   double* dy = l.vecs + 3 * n;
   LsqrState* st = static_cast<LsqrState*>(l.state);
-  hipLaunchKernelGGL(k_lsqr_init, dim3(1), dim3(256), 0, s, n, max_iters, stop, st, q.xw, wpass,
-                     dy);
+  SNS_LAUNCH("lsqr_init", k_lsqr_init, dim3(1), dim3(256), 0, s, n, max_iters, stop, st, q.xw, wpass,
+             dy);
   const size_t lds_step = ((size_t)n + 4096 + 16 + 1024) * sizeof(double);
-  for (int it = 0; it <= max_iters; ++it) {
+  // iteration 0 is the residual pass r0 = b - A x0 plus the start-up step
+  auto enqueue = [&](int it) {
     const void* uin = it == 0 ? b : l.u;
     if (A.dtype == SNS_F64) launch_pass_v<double, 2>(A, p, l, uin, s);
     else launch_pass_v<float, 4>(A, p, l, uin, s);
-    hipLaunchKernelGGL(k_lsqr_step, dim3(1), dim3(1024), lds_step, s, n, p.grid, sighat, q.R,
-                       l.zpart, l.npart, st, wpass, v, wd, dy);
+    SNS_LAUNCH("lsqr_step", k_lsqr_step, dim3(1), dim3(1024), lds_step, s, n, p.grid, sighat, q.R,
+               l.zpart, l.npart, st, wpass, v, wd, dy);
+  };
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  SNS_HIP_TRY(hipStreamIsCapturing(s, &cap));
+  PollRing& ring = poll_ring();
+  if (cap != hipStreamCaptureStatusNone || stop == 0.0 || !ring.ok) {
+    // fixed launch sequence; iterations after the stop rule return at once
+    for (int it = 0; it <= max_iters; ++it) enqueue(it);
+  } else {
+    // Keep at most two iterations in flight.  Before running ahead of an
+    // unread iteration, predict from the geometric decay of the stop ratio
+    // whether that iteration converges; if so, wait for it instead, so that no
+    // launch is issued after the stop rule has fired.
+    const int K = PollRing::kSlots;
+    auto post = [&](int it) {
+      SNS_HIP_TRY(hipMemcpyAsync(&ring.slot[it % K], st, sizeof(LsqrState), hipMemcpyDeviceToHost,
+                                 s));
+      SNS_HIP_TRY(hipEventRecord(ring.ev[it % K], s));
+      return SNS_OK;
+    };
+    double r_prev = -1.0, r_last = -1.0;
+    bool done = false;
+    int known = -1;  // last iteration whose state has been read
+    auto read = [&](int it) {
+      SNS_HIP_TRY(hipEventSynchronize(ring.ev[it % K]));
+      const LsqrState& h = ring.slot[it % K];
+      done = h.done != 0;
+      r_prev = r_last;
+      r_last = h.ratio * (sighat > 0.0 ? sighat : 1.0);
+      known = it;
+      return SNS_OK;
+    };
+    enqueue(0);
+    sns_status e = post(0);
+    if (e != SNS_OK) return e;
+    int next = 1;
+    while (next <= max_iters) {
+      if (known < next - 1) {
+        // state after next-1 unknown: wait for it if it is predicted to stop
+        bool predict_stop = false;
+        if (r_last > 0.0 && r_prev > 0.0) {
+          double qr = r_last / r_prev;
+          qr = qr < 0.2 ? 0.2 : (qr > 0.95 ? 0.95 : qr);
+          // iteration next-1 is one step past the last known ratio
+          predict_stop = r_last * qr <= 2.0 * stop;
+        }
+        if (predict_stop || known < next - 2) {
+          if ((e = read(known + 1)) != SNS_OK) return e;
+          continue;
+        }
+      }
+      if (known == next - 1 && done) break;
+      enqueue(next);
+      if ((e = post(next)) != SNS_OK) return e;
+      ++next;
+      if (known < next - 2) {
+        if ((e = read(next - 2)) != SNS_OK) return e;
+        if (done) break;
+      }
+    }
   }
   const size_t lds_fin = ((size_t)n + 4096) * sizeof(double);
-  hipLaunchKernelGGL(k_lsqr_final, dim3(1), dim3(1024), lds_fin, s, n, q.R, q.xw, dy, st, x,
-                     info_dev);
+  SNS_LAUNCH("lsqr_final", k_lsqr_final, dim3(1), dim3(1024), lds_fin, s, n, q.R, q.xw, dy, st, x,
+             info_dev);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }

@@ -294,11 +294,11 @@ template <int MAXR, int NB>
 void run_panels(int64_t d, int64_t n, const QrBufs& q, hipStream_t st) {
   for (int64_t j0 = 0; j0 < n; j0 += NB) {
     const int nbw = (int)((n - j0) < NB ? (n - j0) : NB);
-    hipLaunchKernelGGL((k_qr_panel<MAXR, NB>), dim3(1), dim3(kPanelThreads), 0, st, d, j0, nbw,
+    SNS_LAUNCH("qr_panel", (k_qr_panel<MAXR, NB>), dim3(1), dim3(kPanelThreads), 0, st, d, j0, nbw,
                        q.M, q.tau, q.T, q.scal);
     const int64_t ntr = n + 1 - (j0 + nbw);
     if (ntr > 0)
-      hipLaunchKernelGGL((k_qr_trailing<NB>), dim3((unsigned)((ntr + 7) / 8)), dim3(256), 0, st,
+      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB>), dim3((unsigned)((ntr + 7) / 8)), dim3(256), 0, st,
                          d, n, j0, nbw, q.M, q.T);
   }
 }
@@ -325,13 +325,13 @@ sns_status launch_qr_solve(int64_t d, int64_t n, sns_dtype dt, const void* SA, i
                            const void* Sb, const QrBufs& q, double* x0, double* Rout,
                            sns_info* info_dev, hipStream_t st) {
   if (d > 8192 || n > 4096) return SNS_ERR_SHAPE;
-  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, q.scal, (int64_t)8);
+  SNS_LAUNCH("zero", k_zero, dim3(1), dim3(64), 0, st, q.scal, (int64_t)8);
   const dim3 lg((unsigned)((d + 31) / 32), (unsigned)((n + 1 + 31) / 32));
   if (dt == SNS_F64)
-    hipLaunchKernelGGL(k_qr_load<double>, lg, dim3(32, 8), 0, st, d, n,
+    SNS_LAUNCH("qr_load", k_qr_load<double>, lg, dim3(32, 8), 0, st, d, n,
                        static_cast<const double*>(SA), ld_sa, static_cast<const double*>(Sb), q.M);
   else
-    hipLaunchKernelGGL(k_qr_load<float>, lg, dim3(32, 8), 0, st, d, n,
+    SNS_LAUNCH("qr_load", k_qr_load<float>, lg, dim3(32, 8), 0, st, d, n,
                        static_cast<const float*>(SA), ld_sa, static_cast<const float*>(Sb), q.M);
   if (d <= 512) run_panels<1, 16>(d, n, q, st);
   else if (d <= 1024) run_panels<2, 16>(d, n, q, st);
@@ -339,7 +339,7 @@ sns_status launch_qr_solve(int64_t d, int64_t n, sns_dtype dt, const void* SA, i
   else if (d <= 4096) run_panels<8, 8>(d, n, q, st);
   else run_panels<16, 4>(d, n, q, st);
   const size_t lds = ((size_t)n + 4096 + 16) * sizeof(double);
-  hipLaunchKernelGGL(k_qr_finish, dim3(1), dim3(1024), lds, st, d, n, q.M, q.R, Rout, x0, q.scal,
+  SNS_LAUNCH("qr_finish", k_qr_finish, dim3(1), dim3(1024), lds, st, d, n, q.M, q.R, Rout, x0, q.scal,
                      info_dev);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;

@@ -1,0 +1,147 @@
+// Per-kernel timing: when enabled, every launch of the library is bracketed by
+// two HIP events recorded on the launch stream.  Durations are read back on
+// demand (sns_timing_summary) and summed per kernel name.  Enabled by
+// sns_timing_enable(1) or by the environment variable SNS_TRACE=1, which also
+// prints the summary to stderr when the process exits.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace sns {
+
+namespace {
+
+struct Rec {
+  const char* name;
+  hipEvent_t a, b;
+};
+
+struct Registry {
+  std::mutex mu;
+  bool on = false;
+  bool env_checked = false;
+  std::vector<hipEvent_t> pool;  // free events
+  std::vector<Rec> recs;
+  std::map<std::string, std::pair<double, long long>> done;  // name -> (ms, launches)
+};
+
+Registry& reg() {
+  static Registry r;
+  return r;
+}
+
+thread_local Rec* t_open = nullptr;
+thread_local Rec t_pending;
+
+hipEvent_t take_event(Registry& r) {
+  if (!r.pool.empty()) {
+    hipEvent_t e = r.pool.back();
+    r.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Fold finished records into the per-name totals (waits for them).
+void collect(Registry& r) {
+  for (Rec& x : r.recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(x.b) == hipSuccess && hipEventElapsedTime(&ms, x.a, x.b) == hipSuccess) {
+      auto& slot = r.done[x.name];
+      slot.first += ms;
+      slot.second += 1;
+    }
+    r.pool.push_back(x.a);
+    r.pool.push_back(x.b);
+  }
+  r.recs.clear();
+}
+
+void print_at_exit() {
+  char buf[8192];
+  sns_timing_summary(buf, sizeof(buf));
+  fputs(buf, stderr);
+}
+
+void check_env(Registry& r) {
+  if (r.env_checked) return;
+  r.env_checked = true;
+  const char* v = getenv("SNS_TRACE");
+  if (v && v[0] == '1') {
+    r.on = true;
+    atexit(print_at_exit);
+  }
+}
+
+}  // namespace
+
+void timing_begin(const char* name, hipStream_t s) {
+  Registry& r = reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  check_env(r);
+  if (!r.on) return;
+  t_pending.name = name;
+  t_pending.a = take_event(r);
+  t_pending.b = take_event(r);
+  if (!t_pending.a || !t_pending.b) return;
+  hipEventRecord(t_pending.a, s);
+  t_open = &t_pending;
+}
+
+void timing_end(hipStream_t s) {
+  if (!t_open) return;
+  Registry& r = reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  hipEventRecord(t_open->b, s);
+  r.recs.push_back(*t_open);
+  t_open = nullptr;
+  if (r.recs.size() > 4096) collect(r);
+}
+
+}  // namespace sns
+
+extern "C" {
+
+void sns_timing_enable(int on) {
+  sns::Registry& r = sns::reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  sns::check_env(r);
+  r.on = on != 0;
+}
+
+void sns_timing_reset(void) {
+  sns::Registry& r = sns::reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  sns::collect(r);
+  r.done.clear();
+}
+
+int sns_timing_summary(char* buf, size_t len) {
+  sns::Registry& r = sns::reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  sns::collect(r);
+  std::string out = "# kernel launches total_ms avg_us\n";
+  char line[256];
+  for (auto& kv : r.done) {
+    snprintf(line, sizeof(line), "%s %lld %.6f %.3f\n", kv.first.c_str(), kv.second.second,
+             kv.second.first, 1000.0 * kv.second.first / (double)(kv.second.second ? kv.second.second : 1));
+    out += line;
+  }
+  if (buf && len) {
+    strncpy(buf, out.c_str(), len - 1);
+    buf[len - 1] = '\0';
+  }
+  return (int)out.size();
+}
+
+}  // extern "C"

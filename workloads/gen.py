@@ -56,27 +56,47 @@ def random_orthogonal(n: int, rng) -> np.ndarray:
     return Q * np.sign(np.diag(R))
 
 
+def _block_rngs(seed: int, nblocks: int):
+    """Independent generators for row blocks (numpy SeedSequence.spawn)."""
+    return [np.random.default_rng(c) for c in np.random.SeedSequence(seed).spawn(nblocks)]
+
+
+def _parallel(fn, items, workers: int = 0):
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    workers = workers or min(16, os.cpu_count() or 4)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fn, items))
+
+
 def dense_ill_conditioned(m: int, n: int, seed: int, cond: float = 1e6, rel_noise: float = 1e-4,
                           dtype=np.float32, block: int = 1 << 16) -> Dense:
     """A = G diag(sigma) V^T with G Gaussian, sigma log-spaced 1 .. 1/cond, V orthogonal.
 
     b = A x_true + rel_noise * (||A x_true|| / ||z||) z with z ~ N(0, I_m).
-    A is built in float64 row blocks and rounded to dtype; b is computed from
-    the rounded A.
+    A is built in float64 row blocks (each block with its own spawned
+    generator, so blocks can be drawn in parallel) and rounded to dtype; b is
+    computed from the rounded A.
     """
-    rng = np.random.default_rng(seed)
+    nblk = (m + block - 1) // block
+    rngs = _block_rngs(seed, nblk + 1)
+    head = rngs[nblk]
     sigma = np.logspace(0.0, -np.log10(cond), n)
-    V = random_orthogonal(n, rng)
+    V = random_orthogonal(n, head)
     W = (sigma[:, None] * V.T)  # diag(sigma) V^T
-    x = rng.standard_normal(n)
+    x = head.standard_normal(n)
     A = np.empty((m, n), dtype=dtype)
     b0 = np.empty(m)
-    for r0 in range(0, m, block):
-        r1 = min(m, r0 + block)
-        G = rng.standard_normal((r1 - r0, n))
+    z = np.empty(m)
+
+    def fill(k):
+        r0, r1 = k * block, min(m, (k + 1) * block)
+        G = rngs[k].standard_normal((r1 - r0, n))
         A[r0:r1] = (G @ W).astype(dtype)
         b0[r0:r1] = A[r0:r1].astype(np.float64) @ x
-    z = rng.standard_normal(m)
+        z[r0:r1] = rngs[k].standard_normal(r1 - r0)
+
+    _parallel(fill, range(nblk))
     b = (b0 + rel_noise * (np.linalg.norm(b0) / np.linalg.norm(z)) * z).astype(dtype)
     return Dense(A, b, x, {"kind": "dense_ill_conditioned", "m": m, "n": n, "seed": seed,
                            "cond": cond, "rel_noise": rel_noise})
