@@ -82,6 +82,8 @@ struct QrBufs {
   double* T;      // nb x nb compact-WY factor of the current panel
   double* tau;    // n
   double* R;      // n x n column-major copy of R (ld n)
+  double* Rr;     // n x n row-major copy of R (ld n)
+  double* invd;   // n: 1 / R_jj
   double* xw;     // n: x0, then scratch
   double* scal;   // small scalars: [0] rho, [1] rank-deficient flag, [2] non-finite flag
 };
@@ -99,13 +101,19 @@ struct LsqrBufs {
   void* u;          // m, A's dtype: the unnormalised Golub-Kahan vector
   double* zpart;    // G x n partial A^T u
   double* npart;    // G partial ||u||^2
-  double* vecs;     // 6 n: w_pass, v, wd, dy, z, scratch
+  double* zred2;    // first-level reduction of zpart
+  double* nred2;    // first-level reduction of npart
+  double* Xc;       // X = R^{-1}, column-major (n x n)
+  double* Xr;       // X = R^{-1}, row-major (n x n)
+  double* ypart;    // per-group shares of ||y||^2 in k_lsqr_xtz
+  double* vecs;     // 6 n: w_pass, v, wd, dy, y, scratch
   void* state;      // LsqrState
 };
 struct LsqrPlan {
   int grid = 512;   // work-groups of the fused pass
   int lpr = 16;     // lanes per row
   int nch = 4;      // column chunks per lane (a chunk is 16 bytes per lane)
+  int unroll = 1;   // rows per slot and step (1 or 2)
 };
 LsqrPlan make_lsqr_plan(const sns_matrix& A);
 size_t lsqr_workspace_bytes(const sns_matrix& A, const LsqrPlan& p);

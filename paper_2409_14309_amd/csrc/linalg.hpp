@@ -7,115 +7,115 @@
 
 namespace sns {
 
-// Reduce NB values per lane over the 64 lanes of a wave with a butterfly that
-// halves the live values at each of the first log2(NB) exchanges.  On return
-// `out` on lane L is the wave total of value index `idx(L)`; every index is
-// held by 64 / NB lanes.  Exchange order is fixed, so the result is
-// reproducible.
-template <int NB>
-__device__ __forceinline__ double wave_reduce_multi(const double (&g)[NB], int& idx) {
-  static_assert(NB >= 1 && NB <= 64 && (NB & (NB - 1)) == 0, "NB power of two");
-  const int lane = threadIdx.x & 63;
-  double cur[NB];
-#pragma unroll
-  for (int q = 0; q < NB; ++q) cur[q] = g[q];
-  int id = 0;
-  int s = 0;
-#pragma unroll
-  for (int len = NB; len > 1; len >>= 1, ++s) {
-    const int mask = 32 >> s;
-    const bool up = (lane & mask) != 0;
-    id = (id << 1) | (up ? 1 : 0);
-#pragma unroll
-    for (int q = 0; q < len / 2; ++q) {
-      const double send = up ? cur[q] : cur[q + len / 2];
-      const double keep = up ? cur[q + len / 2] : cur[q];
-      cur[q] = keep + __shfl_xor(send, mask, 64);
-    }
-  }
-#pragma unroll
-  for (int mask = 32 >> s; mask >= 1; mask >>= 1) cur[0] += __shfl_xor(cur[0], mask, 64);
-  idx = id;
-  return cur[0];
-}
-
-// Sum NB values per thread over the whole work-group; tot[0..NB) (LDS) gets the
-// totals, visible to all threads on return.  red: LDS of (blockDim/64) * NB.
-template <int NB>
+// Sum NB values per thread over a work-group of NT threads; tot[0..NB) (LDS)
+// gets the totals, visible to all threads on return.  red: LDS of NB * NT
+// doubles.  The values are transposed through LDS: value c is summed by the
+// P = NT / NB consecutive threads of group c, each adding NB stored entries
+// in order, and the group finishes with an xor-shuffle over its P lanes.  The
+// order is fixed, so the result is reproducible.
+template <int NB, int NT>
 __device__ __forceinline__ void block_reduce_multi(const double (&g)[NB], double* red,
                                                    double* tot) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int idx;
-  const double v = wave_reduce_multi<NB>(g, idx);
-  if ((lane & (64 / NB - 1)) == 0) red[wv * NB + idx] = v;
+  static_assert((NB & (NB - 1)) == 0 && NB <= NT && NT % 64 == 0, "NB power of two");
+  constexpr int P = NT / NB;
+  constexpr int PW = P < 64 ? P : 64;  // lanes of one group inside a wave
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < NB; ++c) red[c * NT + t] = g[c];
   __syncthreads();
-  if (threadIdx.x < NB) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += red[w * NB + threadIdx.x];
-    tot[threadIdx.x] = t;
+  const int c = t / P, p = t % P;
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) s += red[c * NT + p * NB + q];
+#pragma unroll
+  for (int off = PW / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if constexpr (P <= 64) {
+    if (p == 0) tot[c] = s;
+  } else {
+    // a group spans P / 64 whole waves: combine their totals in wave order
+    __syncthreads();
+    if ((t & 63) == 0) red[t >> 6] = s;
+    __syncthreads();
+    if (t < NB) {
+      double u = 0.0;
+      for (int w = 0; w < P / 64; ++w) u += red[t * (P / 64) + w];
+      tot[t] = u;
+    }
   }
   __syncthreads();
 }
 
-// Solve R x = c in place (x in LDS, length n) by back substitution, 64 rows
-// at a time: wave 0 solves the diagonal block from an LDS copy `blk`
-// (64 x 64 doubles), then the whole group updates the rows above it.
-__device__ inline void trsv_upper_lds(const double* __restrict__ R, int64_t ld, int n,
-                                      double* x, double* blk) {
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
-  for (int bend = n; bend > 0; bend -= 64) {
-    const int b0 = bend > 64 ? bend - 64 : 0, bw = bend - b0;
-    for (int e = tid; e < 64 * 64; e += nt) {
-      const int r = e & 63, c = e >> 6;  // blk[c * 64 + r] = R[b0 + r, b0 + c]
-      blk[e] = (r < bw && c < bw) ? R[(int64_t)(b0 + c) * ld + b0 + r] : 0.0;
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Triangular solve in place on a vector x in LDS (length n) by one work-group
+// of NT threads, 64 unknowns at a time.  `C` is the triangular factor in
+// column-major order with leading dimension ld, `invd` the reciprocals of its
+// diagonal.
+//   UPPER = true : C = R,   back substitution  R x = c  (last unknown first)
+//   UPPER = false: C = R^T (i.e. R stored row-major), forward substitution
+//                  R^T y = z (first unknown first)
+// The 64 x 64 diagonal block is staged in LDS as blk[j * 64 + l] =
+// C[b0 + l, b0 + j] (all loads issued before the stores); wave 0 runs the
+// substitution chain, reading each solved unknown with v_readlane; then the
+// group updates the remaining rows with coalesced reads of C, 16 loads in
+// flight per thread.  The order of operations is fixed.
+template <bool UPPER, int NT>
+__device__ inline void trsv_lds(const double* __restrict__ C, int64_t ld, int n,
+                                const double* __restrict__ invd, double* x, double* blk) {
+  static_assert(4096 % NT == 0, "NT divides 4096");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int nblk = (n + 63) / 64;
+  for (int bi = 0; bi < nblk; ++bi) {
+    // UPPER walks the blocks from the bottom; the top block may be partial
+    const int b0 = UPPER ? (n - 64 * (bi + 1) > 0 ? n - 64 * (bi + 1) : 0) : 64 * bi;
+    const int bend = UPPER ? n - 64 * bi : (b0 + 64 < n ? b0 + 64 : n);
+    const int bw = bend - b0;
+    {
+      constexpr int K = 4096 / NT;
+      double tmp[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int e = tid + k * NT, l = e & 63, j = e >> 6;
+        tmp[k] = (l < bw && j < bw) ? C[(int64_t)(b0 + j) * ld + b0 + l] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) blk[tid + k * NT] = tmp[k];
     }
     __syncthreads();
     if (tid < 64) {
       double xi = lane < bw ? x[b0 + lane] : 0.0;
-      for (int jl = bw - 1; jl >= 0; --jl) {
-        const double xj = __shfl(xi, jl, 64) / blk[jl * 64 + jl];
-        if (lane == jl) xi = xj;
-        else if (lane < jl) xi -= blk[jl * 64 + lane] * xj;
+      const double di = lane < bw ? invd[b0 + lane] : 0.0;
+#pragma unroll 8
+      for (int q = 0; q < 64; ++q) {
+        const int jl = UPPER ? 63 - q : q;
+        if (jl < bw) {
+          const double xj = readlane_f64(xi * di, jl);
+          const double cj = blk[jl * 64 + lane];
+          const bool upd = UPPER ? lane < jl : lane > jl;
+          xi = lane == jl ? xj : (upd ? fma(-cj, xj, xi) : xi);
+        }
       }
       if (lane < bw) x[b0 + lane] = xi;
     }
     __syncthreads();
-    for (int i = tid; i < b0; i += nt) {
+    // remaining unknowns: above the block (UPPER) or below it (lower)
+    const int r0 = UPPER ? 0 : bend, r1 = UPPER ? b0 : n;
+    for (int i = r0 + tid; i < r1; i += NT) {
       double s = 0.0;
-      for (int j = b0; j < bend; ++j) s += R[(int64_t)j * ld + i] * x[j];
-      x[i] -= s;
-    }
-    __syncthreads();
-  }
-}
-
-// Solve R^T y = z in place (y in LDS) by forward substitution, 64 rows at a
-// time.  R^T[i, j] = R[j, i] = R[i * ld + j] (column-major R).
-__device__ inline void trsv_upper_trans_lds(const double* __restrict__ R, int64_t ld, int n,
-                                            double* y, double* blk) {
-  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
-  for (int b0 = 0; b0 < n; b0 += 64) {
-    const int bend = b0 + 64 < n ? b0 + 64 : n, bw = bend - b0;
-    for (int e = tid; e < 64 * 64; e += nt) {
-      const int r = e & 63, c = e >> 6;  // blk[c * 64 + r] = R^T[b0 + c, b0 + r] = R[b0 + r, b0 + c]
-      blk[e] = (r < bw && c < bw) ? R[(int64_t)(b0 + c) * ld + b0 + r] : 0.0;
-    }
-    __syncthreads();
-    if (tid < 64) {
-      double yi = lane < bw ? y[b0 + lane] : 0.0;
-      for (int jl = 0; jl < bw; ++jl) {
-        const double yj = __shfl(yi, jl, 64) / blk[jl * 64 + jl];
-        if (lane == jl) yi = yj;
-        else if (lane > jl && lane < bw) yi -= blk[lane * 64 + jl] * yj;  // R[b0+jl, b0+lane]
+      int j = b0;
+      for (; j + 16 <= bend; j += 16) {
+        double c[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c[u] = C[(int64_t)(j + u) * ld + i];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s = fma(c[u], x[j + u], s);
       }
-      if (lane < bw) y[b0 + lane] = yi;
-    }
-    __syncthreads();
-    for (int i = bend + tid; i < n; i += nt) {
-      double s = 0.0;
-      const double* Ri = R + (int64_t)i * ld;  // column i of R: R[j, i] for j < i
-      for (int j = b0; j < bend; ++j) s += Ri[j] * y[j];
-      y[i] -= s;
+      for (; j < bend; ++j) s = fma(C[(int64_t)j * ld + i], x[j], s);
+      x[i] -= s;
     }
     __syncthreads();
   }

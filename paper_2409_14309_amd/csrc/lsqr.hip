@@ -1,11 +1,17 @@
 // SAP-SAS refinement: LSQR (Paige and Saunders 1982) on the right-
-// preconditioned operator Abar = A R^{-1}, R from the QR of the sketch,
+// preconditioned operator A X with X = R^{-1}, R from the QR of the sketch,
 // starting from the sketch-and-solve answer x0 (sketch-and-precondition, as
 // named in the paper's solver list).
 //
+// X is formed once per solve (k_tri_inv, fp64 back substitution per column)
+// and applied as matrix-vector products by many work-groups.  LSQR runs on the
+// fixed operator A X and the answer is mapped back with the same X,
+// x = x0 + X dy, so x is the least-squares solution of A x = b whatever the
+// rounding in X; X only has to keep A X well conditioned.
+//
 // One pass over A per LSQR iteration.  The bidiagonalisation needs
 // u_{i+1} = (Abar v_i - alpha_i u_i) / beta_{i+1} and then Abar^T u_{i+1}.
-// The pass computes the unnormalised u' = A w - gamma u (w = R^{-1} v_i,
+// The pass computes the unnormalised u' = A w - gamma u (w = X v_i,
 // gamma = alpha_i / beta_i because u is kept unnormalised), and in the same
 // sweep over the rows accumulates A^T u' and ||u'||^2; dividing by
 // beta_{i+1} = ||u'|| afterwards gives A^T u_{i+1}.  This is the same
@@ -13,13 +19,16 @@
 // accumulation.  The residual r0 = b - A x0 and A^T r0 come from the same
 // kernel with w = -x0, gamma = -1 and u = b.
 //
-// Precision: A and the m-vector u are stored in A's dtype; every product and
-// accumulation is fp64, and all n-vectors are fp64.
+// Per iteration: k_lsqr_pass (all of A), k_lsqr_reduce (partials of A^T u'),
+// k_lsqr_xtz (y = X^T z / beta - beta v; the last work-group to finish runs
+// the scalar recurrences and the n-vector updates), k_lsqr_xv (w = X v).
 //
-// The scalar recurrences, the triangular solves with R and R^T, and the stop
-// test run in one work-group (k_lsqr_step).  Once the stop rule holds, a flag
-// in device memory makes the remaining launches return at once.
+// Precision: A and the m-vector u are stored in A's dtype; every product and
+// accumulation is fp64, and all n-vectors are fp64.  Once the stop rule
+// holds, a flag in device memory makes the remaining launches return at once.
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -32,6 +41,7 @@ struct LsqrState {
   double ratio;      // alpha_{k+1} |c_k| / sigma_hat at the last iteration
   double stop;       // rtol * sigma_hat (0: run max_iters)
   int iter, max_iters, done, status;
+  unsigned int arrived;  // work-groups of k_lsqr_xtz done (reset by the last)
 };
 
 namespace {
@@ -48,17 +58,40 @@ template <>
 struct VecT<double, 1> { using type = double; };
 
 constexpr int kPassWaves = 4;
+constexpr int kRedSplit = 16;      // partial groups left for the step kernel
+
+template <typename T, int VEC, int NCH, int LPR>
+__device__ __forceinline__ void load_row_chunks(const T* __restrict__ row, int lr, int n,
+                                                T (&a)[NCH][VEC]) {
+  constexpr int CW = LPR * VEC;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    const int col = c * CW + lr * VEC;
+    if (col + VEC <= n) {
+      using V = typename VecT<T, VEC>::type;
+      const V x = *reinterpret_cast<const V*>(row + col);
+      const T* xe = reinterpret_cast<const T*>(&x);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) a[c][e] = xe[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) a[c][e] = (col + e < n) ? row[col + e] : T(0);
+    }
+  }
+}
 
 // Fused pass: for each row i of this work-group's contiguous row range,
 //   t = A[i,:] . w;  u'[i] = t - gamma * uin[i];  z += A[i,:]^T u'[i];
-//   nrm += u'[i]^2.  Per-group z and nrm go to zpart / npart.
-template <typename T, int VEC, int LPR, int NCH>
+//   nrm += u'[i]^2.  Per-group z and nrm go to zpart / npart.  A row is
+// spread over LPR lanes (NCH 16-byte chunks each); each row slot handles two
+// rows per step so that two rows' loads are in flight together.
+template <typename T, int VEC, int LPR, int NCH, int U>
 __global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(
     const T* __restrict__ A, int64_t ld, int64_t m, int n, const LsqrState* __restrict__ st,
     const double* __restrict__ wv, const T* __restrict__ uin, T* __restrict__ uout,
     double* __restrict__ zpart, double* __restrict__ npart) {
   constexpr int RPW = 64 / LPR;
-  constexpr int CW = LPR * VEC;        // columns per chunk
+  constexpr int CW = LPR * VEC;          // columns per chunk
   constexpr int NSL = kPassWaves * RPW;  // row slots per group
   __shared__ double zred[kPassWaves][NCH * CW];
   __shared__ double nred[kPassWaves];
@@ -80,39 +113,74 @@ __global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(
 
   const int64_t r0 = m * (int64_t)blockIdx.x / gridDim.x;
   const int64_t r1 = m * (int64_t)(blockIdx.x + 1) / gridDim.x;
-  for (int64_t i = r0 + slot; i < r1; i += NSL) {
-    const T* row = A + i * ld;
-    T a[NCH][VEC];
+  if constexpr (U == 1) {
+    for (int64_t i = r0 + slot; i < r1; i += NSL) {
+      T a0[NCH][VEC];
+      load_row_chunks<T, VEC, NCH, LPR>(A + i * ld, lr, n, a0);
+      const double u0 = (double)uin[i];
+      double t0 = 0.0;
 #pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-      const int col = c * CW + lr * VEC;
-      if (col + VEC <= n) {
-        using V = typename VecT<T, VEC>::type;
-        const V x = *reinterpret_cast<const V*>(row + col);
-        const T* xe = reinterpret_cast<const T*>(&x);
+      for (int c = 0; c < NCH; ++c)
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) a[c][e] = xe[e];
-      } else {
+        for (int e = 0; e < VEC; ++e) t0 = fma((double)a0[c][e], w[c][e], t0);
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) a[c][e] = (col + e < n) ? row[col + e] : T(0);
+      for (int off = 1; off < LPR; off <<= 1) t0 += __shfl_xor(t0, off, 64);
+      const double p0 = t0 - gamma * u0;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) z[c][e] = fma((double)a0[c][e], p0, z[c][e]);
+      if (lr == 0) {
+        uout[i] = (T)p0;
+        nrm = fma(p0, p0, nrm);
       }
     }
-    const double ui = (double)uin[i];
-    double t = 0.0;
+  } else {
+    for (int64_t i = r0 + slot; i < r1; i += 2 * NSL) {
+      const int64_t i2 = i + NSL;
+      const bool has2 = i2 < r1;
+      T a0[NCH][VEC], a1[NCH][VEC];
+      load_row_chunks<T, VEC, NCH, LPR>(A + i * ld, lr, n, a0);
+      if (has2) {
+        load_row_chunks<T, VEC, NCH, LPR>(A + i2 * ld, lr, n, a1);
+      } else {
 #pragma unroll
-    for (int c = 0; c < NCH; ++c)
+        for (int c = 0; c < NCH; ++c)
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) t = fma((double)a[c][e], w[c][e], t);
+          for (int e = 0; e < VEC; ++e) a1[c][e] = T(0);
+      }
+      const double u0 = (double)uin[i];
+      const double u1 = has2 ? (double)uin[i2] : 0.0;
+      double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-    for (int off = 1; off < LPR; off <<= 1) t += __shfl_xor(t, off, 64);
-    const double up = t - gamma * ui;
+      for (int c = 0; c < NCH; ++c)
 #pragma unroll
-    for (int c = 0; c < NCH; ++c)
+        for (int e = 0; e < VEC; ++e) {
+          t0 = fma((double)a0[c][e], w[c][e], t0);
+          t1 = fma((double)a1[c][e], w[c][e], t1);
+        }
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) z[c][e] = fma((double)a[c][e], up, z[c][e]);
-    if (lr == 0) {
-      uout[i] = (T)up;
-      nrm = fma(up, up, nrm);
+      for (int off = 1; off < LPR; off <<= 1) {
+        t0 += __shfl_xor(t0, off, 64);
+        t1 += __shfl_xor(t1, off, 64);
+      }
+      const double p0 = t0 - gamma * u0;
+      const double p1 = t1 - gamma * u1;
+#pragma unroll
+      for (int c = 0; c < NCH; ++c)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          z[c][e] = fma((double)a0[c][e], p0, z[c][e]);
+          z[c][e] = fma((double)a1[c][e], p1, z[c][e]);
+        }
+      if (lr == 0) {
+        uout[i] = (T)p0;
+        nrm = fma(p0, p0, nrm);
+        if (has2) {
+          uout[i2] = (T)p1;
+          nrm = fma(p1, p1, nrm);
+        }
+      }
     }
   }
   // combine the row slots of a wave (lanes with equal lr), then the waves
@@ -145,6 +213,50 @@ __global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(
   }
 }
 
+// First level of the reduction of the G per-group partials: work-group
+// (cx, s) sums partials [s G / S, (s+1) G / S) for columns [64 cx, 64 cx + 64)
+// into zred2[s][.] (and, for cx = 0, the norms into nred2[s]).  Four thread
+// groups take every fourth partial, each with eight running sums (partials
+// g, g + 4, ..., g + 28 of a round of 32); all sums are combined in a fixed
+// order.
+__global__ __launch_bounds__(256) void k_lsqr_reduce(int n, int G,
+                                                     const LsqrState* __restrict__ st,
+                                                     const double* __restrict__ zpart,
+                                                     const double* __restrict__ npart,
+                                                     double* __restrict__ zred2,
+                                                     double* __restrict__ nred2) {
+  __shared__ double part[4][64];
+  __shared__ double red[4];
+  if (st->done) return;
+  const int t = threadIdx.x, cl = t & 63, grp = t >> 6;
+  const int s = blockIdx.y;
+  const int g0 = (int)((int64_t)G * s / kRedSplit), g1 = (int)((int64_t)G * (s + 1) / kRedSplit);
+  const int col = blockIdx.x * 64 + cl;
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  if (col < n) {
+    int g = g0 + grp;
+    for (; g + 28 < g1; g += 32) {
+      double v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = zpart[(size_t)(g + 4 * k) * n + col];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc[k] += v[k];
+    }
+    for (int k = 0; g < g1; g += 4, ++k) acc[k] += zpart[(size_t)g * n + col];
+  }
+  part[grp][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+  __syncthreads();
+  if (t < 64 && col < n) zred2[(size_t)s * n + col] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+  if (blockIdx.x == 0) {
+    double a = 0.0;
+    for (int g = g0 + t; g < g1; g += 256) a += npart[g];
+    a = block_sum(a, red);
+    if (t == 0) nred2[s] = a;
+  }
+}
+
 __global__ void k_lsqr_init(int n, int max_iters, double stop, LsqrState* st,
                             const double* __restrict__ x0, double* __restrict__ wpass,
                             double* __restrict__ dy) {
@@ -161,82 +273,119 @@ __global__ void k_lsqr_init(int n, int max_iters, double stop, LsqrState* st,
     st->max_iters = max_iters;
     st->done = max_iters <= 0 ? 1 : 0;
     st->status = SNS_OK;
+    st->arrived = 0u;
   }
 }
 
-// One LSQR step after a pass.  Vectors (fp64, length n): wpass, v, wd, dy.
-__global__ __launch_bounds__(1024) void k_lsqr_step(int n, int G, double sighat,
-                                                    const double* __restrict__ R,
-                                                    const double* __restrict__ zpart,
-                                                    const double* __restrict__ npart,
-                                                    LsqrState* __restrict__ st,
-                                                    double* __restrict__ wpass,
-                                                    double* __restrict__ v,
-                                                    double* __restrict__ wd,
-                                                    double* __restrict__ dy) {
+// X = R^{-1}: work-group j solves R x = e_j on the leading (j+1) x (j+1)
+// block by back substitution and writes column j of X (column-major Xc and
+// row-major Xr; X is upper triangular).
+constexpr int kInvThreads = 64;
+__global__ __launch_bounds__(kInvThreads) void k_tri_inv(int n, const double* __restrict__ Rc,
+                                                         const double* __restrict__ invd,
+                                                         double* __restrict__ Xc,
+                                                         double* __restrict__ Xr) {
   extern __shared__ double sh[];
-  double* y = sh;                 // n
-  double* blk = sh + n;           // 64 x 64
-  double* red = blk + 4096;       // 16
-  double* part = red + 16;        // up to 1024
+  double* x = sh;        // n
+  double* blk = sh + n;  // 64 x 64
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += kInvThreads) x[i] = i == j ? 1.0 : 0.0;
+  __syncthreads();
+  trsv_lds<true, kInvThreads>(Rc, n, j + 1, invd, x, blk);
+  for (int i = threadIdx.x; i < n; i += kInvThreads) {
+    const double v = i <= j ? x[i] : 0.0;
+    Xc[(int64_t)j * n + i] = v;
+    Xr[(int64_t)i * n + j] = v;
+  }
+}
+
+constexpr int kGemvThreads = 256;
+constexpr int kGemvRows = 16;  // rows per work-group (4 per wave)
+
+// Dot product of row i of a triangular matrix stored row-contiguously
+// (M[i * n + j]) with vec over j in [j0, j1), by one wave; all lanes get it.
+__device__ __forceinline__ double wave_row_dot(const double* __restrict__ M, int n, int i, int j0,
+                                               int j1, const double* __restrict__ vec) {
+  const int lane = threadIdx.x & 63;
+  const double* row = M + (int64_t)i * n;
+  double s = 0.0;
+  for (int j = j0 + lane; j < j1; j += 64) s = fma(row[j], vec[j], s);
+  return wave_sum(s);
+}
+
+// y = X^T (z / beta) - beta v (first step: X^T (z / beta)), z = sum of the
+// reduction splits.  X^T row i = X column i = Xc[i * n + j], j <= i.  Each
+// group writes its rows of y and its share of ||y||^2; the last group to
+// finish (arrival counter) then runs the scalar recurrences and the n-vector
+// updates for the whole vector in a fixed order.
+__global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(
+    int n, double sighat, const double* __restrict__ Xc, const double* __restrict__ zred2,
+    const double* __restrict__ nred2, LsqrState* __restrict__ st, double* __restrict__ zbuf,
+    double* __restrict__ ybuf, double* __restrict__ ypart, double* __restrict__ v,
+    double* __restrict__ wd, double* __restrict__ dy) {
+  extern __shared__ double sh[];
+  double* z = sh;        // n
+  double* red = sh + n;  // 16 + kGemvRows
+  __shared__ bool last;
   if (st->done) return;
-  const int t = threadIdx.x, nt = blockDim.x;
-  // z = sum_g zpart[g]: columns are taken in tiles of `nc`; inside a tile,
-  // thread t sums column t % nc over the partials g = t / nc (mod K), and the
-  // K sums are added in order.
-  const int nc = n < nt ? n : nt;
-  const int K = nt / nc;
-  for (int j0 = 0; j0 < n; j0 += nc) {
-    const int jl = t % nc, kk = t / nc, j = j0 + jl;
-    double s = 0.0;
-    if (kk < K && j < n)
-      for (int g = kk; g < G; g += K) s += zpart[(size_t)g * n + j];
-    if (kk < K) part[kk * nc + jl] = s;
-    __syncthreads();
-    if (t < nc && j0 + t < n) {
-      double tot = 0.0;
-      for (int q = 0; q < K; ++q) tot += part[q * nc + t];
-      y[j0 + t] = tot;
-    }
-    __syncthreads();
-  }
-  double ps = 0.0;
-  for (int g = t; g < G; g += nt) ps += npart[g];
-  const double beta = sqrt(block_sum(ps, red));
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
+  double beta2 = 0.0;
+  for (int s = 0; s < kRedSplit; ++s) beta2 += nred2[s];
+  const double beta = sqrt(beta2);
+  const double invb = beta > 0.0 ? 1.0 / beta : 0.0;
   const bool first = st->iter < 0;
-  if (!isfinite(beta)) {
-    if (t == 0) { st->status = SNS_ERR_NUMERICAL; st->done = 1; }
-    return;
-  }
-  // y = R^{-T} (z / beta) - beta v   (first step: without the beta v term)
-  if (beta > 0.0) {
-    for (int j = t; j < n; j += nt) y[j] /= beta;
-    __syncthreads();
-    trsv_upper_trans_lds(R, n, n, y, blk);
-    if (!first)
-      for (int j = t; j < n; j += nt) y[j] -= beta * v[j];
-  } else {
-    for (int j = t; j < n; j += nt) y[j] = 0.0;
+  for (int j = t; j < n; j += nt) {
+    double a = 0.0;
+    for (int s = 0; s < kRedSplit; ++s) a += zred2[(size_t)s * n + j];
+    z[j] = a * invb;
   }
   __syncthreads();
-  double ss = 0.0;
-  for (int j = t; j < n; j += nt) ss += y[j] * y[j];
-  const double alpha = sqrt(block_sum(ss, red));
-  if (!isfinite(alpha)) {
-    if (t == 0) { st->status = SNS_ERR_NUMERICAL; st->done = 1; }
+  double ysq = 0.0;
+  for (int r = wv; r < kGemvRows; r += nt / 64) {
+    const int i = blockIdx.x * kGemvRows + r;
+    if (i < n) {
+      double yi = wave_row_dot(Xc, n, i, 0, i + 1, z);
+      if (!first) yi -= beta * v[i];
+      if (lane == 0) {
+        ybuf[i] = yi;
+        red[16 + r] = yi * yi;
+      }
+    } else if (lane == 0) {
+      red[16 + r] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int r = 0; r < kGemvRows; ++r) ysq += red[16 + r];
+    ypart[blockIdx.x] = ysq;
+    __threadfence();
+    const unsigned int prev = atomicAdd(&st->arrived, 1u);
+    last = prev == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // ---- last group: scalars and n-vector updates ----
+  double a2 = 0.0;
+  for (int g = 0; g < (int)gridDim.x; ++g) a2 += ypart[g];  // same value on every thread
+  const double alpha = sqrt(a2);
+  if (!isfinite(beta) || !isfinite(alpha)) {
+    if (t == 0) {
+      st->status = SNS_ERR_NUMERICAL;
+      st->done = 1;
+      st->arrived = 0u;
+    }
     return;
   }
   const double inva = alpha > 0.0 ? 1.0 / alpha : 0.0;
   if (first) {
     // beta_1 u_1 = r0, alpha_1 v_1 = Abar^T u_1, wd_1 = v_1, phibar = beta_1, rhobar = alpha_1
     for (int j = t; j < n; j += nt) {
-      const double vj = y[j] * inva;
+      const double vj = ybuf[j] * inva;
       v[j] = vj;
       wd[j] = vj;
       dy[j] = 0.0;
-      y[j] = vj;
     }
-    __syncthreads();
     if (t == 0) {
       st->beta = beta;
       st->alpha = alpha;
@@ -255,14 +404,12 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(int n, int G, double sighat,
     const double phi = c * phibar;
     const double f1 = phi / rho, f2 = theta / rho;
     for (int j = t; j < n; j += nt) {
-      const double vj = y[j] * inva;
+      const double vj = ybuf[j] * inva;
       const double wdj = wd[j];
       dy[j] += f1 * wdj;
       wd[j] = vj - f2 * wdj;
       v[j] = vj;
-      y[j] = vj;
     }
-    __syncthreads();
     if (t == 0) {
       st->beta = beta;
       st->alpha = alpha;
@@ -281,63 +428,82 @@ __global__ __launch_bounds__(1024) void k_lsqr_step(int n, int G, double sighat,
       }
     }
   }
-  __syncthreads();
-  // next pass direction: wpass = R^{-1} v
-  trsv_upper_lds(R, n, n, y, blk);
-  for (int j = t; j < n; j += nt) wpass[j] = y[j];
+  if (t == 0) st->arrived = 0u;
 }
 
-// x = x0 + R^{-1} dy; report.
-__global__ __launch_bounds__(1024) void k_lsqr_final(int n, const double* __restrict__ R,
-                                                     const double* __restrict__ x0,
-                                                     const double* __restrict__ dy,
-                                                     const LsqrState* __restrict__ st,
-                                                     double* __restrict__ x,
-                                                     sns_info* __restrict__ info) {
+// w = X v for the next pass: row i of X = Xr[i * n + j], j >= i.  `out`
+// receives w; with add0 set, out = add0 + X v (the final x = x0 + X dy).
+__global__ __launch_bounds__(kGemvThreads) void k_lsqr_xv(int n, const double* __restrict__ Xr,
+                                                          const double* __restrict__ vin,
+                                                          const double* __restrict__ add0,
+                                                          const LsqrState* __restrict__ st,
+                                                          int skip_if_done,
+                                                          double* __restrict__ out) {
   extern __shared__ double sh[];
-  double* y = sh;
-  double* blk = sh + n;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) y[j] = dy[j];
+  double* vec = sh;  // n
+  if (skip_if_done && st->done) return;
+  const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
+  for (int j = t; j < n; j += nt) vec[j] = vin[j];
   __syncthreads();
-  trsv_upper_lds(R, n, n, y, blk);
-  for (int j = threadIdx.x; j < n; j += blockDim.x) x[j] = x0[j] + y[j];
-  if (threadIdx.x == 0) {
-    info->iters = st->iter < 0 ? 0 : st->iter;
-    info->rel_resid_est = st->ratio;
-    if (info->status == SNS_OK) info->status = st->status;
+  for (int r = wv; r < kGemvRows; r += nt / 64) {
+    const int i = blockIdx.x * kGemvRows + r;
+    if (i < n) {
+      const double wi = wave_row_dot(Xr, n, i, i, n, vec);
+      if (lane == 0) out[i] = add0 ? add0[i] + wi : wi;
+    }
   }
 }
 
-template <typename T, int VEC, int LPR, int NCH>
+__global__ void k_lsqr_report(const LsqrState* __restrict__ st, sns_info* __restrict__ info) {
+  info->iters = st->iter < 0 ? 0 : st->iter;
+  info->rel_resid_est = st->ratio;
+  if (info->status == SNS_OK) info->status = st->status;
+}
+
+template <typename T, int VEC, int LPR, int NCH, int U>
 void launch_pass_t(const sns_matrix& A, const LsqrPlan& p, const LsqrBufs& l, const void* uin,
                    hipStream_t s) {
   double* vecs = l.vecs;
-  SNS_LAUNCH("lsqr_pass", (k_lsqr_pass<T, VEC, LPR, NCH>), dim3(p.grid), dim3(kPassWaves * 64), 0, s,
-                     static_cast<const T*>(A.values), A.ld, A.m, (int)A.n,
-                     static_cast<const LsqrState*>(l.state), vecs, static_cast<const T*>(uin),
-                     static_cast<T*>(l.u), l.zpart, l.npart);
+  SNS_LAUNCH("lsqr_pass", (k_lsqr_pass<T, VEC, LPR, NCH, U>), dim3(p.grid), dim3(kPassWaves * 64),
+             0, s, static_cast<const T*>(A.values), A.ld, A.m, (int)A.n,
+             static_cast<const LsqrState*>(l.state), vecs, static_cast<const T*>(uin),
+             static_cast<T*>(l.u), l.zpart, l.npart);
+}
+
+template <typename T, int VEC, int U>
+void launch_pass_u(const sns_matrix& A, const LsqrPlan& p, const LsqrBufs& l, const void* uin,
+                   hipStream_t s) {
+  switch (p.lpr * 16 + p.nch) {
+    case 4 * 16 + 1: launch_pass_t<T, VEC, 4, 1, U>(A, p, l, uin, s); break;
+    case 4 * 16 + 2: launch_pass_t<T, VEC, 4, 2, U>(A, p, l, uin, s); break;
+    case 4 * 16 + 4: launch_pass_t<T, VEC, 4, 4, U>(A, p, l, uin, s); break;
+    case 8 * 16 + 4: launch_pass_t<T, VEC, 8, 4, U>(A, p, l, uin, s); break;
+    case 16 * 16 + 1: launch_pass_t<T, VEC, 16, 1, U>(A, p, l, uin, s); break;
+    case 16 * 16 + 2: launch_pass_t<T, VEC, 16, 2, U>(A, p, l, uin, s); break;
+    case 16 * 16 + 4: launch_pass_t<T, VEC, 16, 4, U>(A, p, l, uin, s); break;
+    case 32 * 16 + 1: launch_pass_t<T, VEC, 32, 1, U>(A, p, l, uin, s); break;
+    case 32 * 16 + 2: launch_pass_t<T, VEC, 32, 2, U>(A, p, l, uin, s); break;
+    case 32 * 16 + 4: launch_pass_t<T, VEC, 32, 4, U>(A, p, l, uin, s); break;
+    case 64 * 16 + 1: launch_pass_t<T, VEC, 64, 1, U>(A, p, l, uin, s); break;
+    case 64 * 16 + 2: launch_pass_t<T, VEC, 64, 2, U>(A, p, l, uin, s); break;
+    case 64 * 16 + 4: launch_pass_t<T, VEC, 64, 4, U>(A, p, l, uin, s); break;
+    default: launch_pass_t<T, VEC, 64, 8, U>(A, p, l, uin, s); break;
+  }
 }
 
 template <typename T, int VEC>
 void launch_pass_v(const sns_matrix& A, const LsqrPlan& p, const LsqrBufs& l, const void* uin,
                    hipStream_t s) {
-  const int nch = p.nch;
-  switch (p.lpr * 16 + nch) {
-    case 4 * 16 + 1: launch_pass_t<T, VEC, 4, 1>(A, p, l, uin, s); break;
-    case 4 * 16 + 2: launch_pass_t<T, VEC, 4, 2>(A, p, l, uin, s); break;
-    case 4 * 16 + 4: launch_pass_t<T, VEC, 4, 4>(A, p, l, uin, s); break;
-    case 8 * 16 + 4: launch_pass_t<T, VEC, 8, 4>(A, p, l, uin, s); break;
-    case 16 * 16 + 4: launch_pass_t<T, VEC, 16, 4>(A, p, l, uin, s); break;
-    case 32 * 16 + 4: launch_pass_t<T, VEC, 32, 4>(A, p, l, uin, s); break;
-    case 64 * 16 + 4: launch_pass_t<T, VEC, 64, 4>(A, p, l, uin, s); break;
-    default: launch_pass_t<T, VEC, 64, 8>(A, p, l, uin, s); break;
-  }
+  if (p.unroll == 2) launch_pass_u<T, VEC, 2>(A, p, l, uin, s);
+  else launch_pass_u<T, VEC, 1>(A, p, l, uin, s);
 }
 
 }  // namespace
 
-// Plan: lanes per row (lpr) and 16-byte column chunks per lane (nch).  The
-// element vector width is 16 bytes when rows are 16-byte aligned.
+// Plan: lanes per row (lpr) and 16-byte column chunks per lane (nch) such
+// that lpr * nch * (16 / element size) covers n; work-groups of the pass.
+// SNS_LSQR_PLAN="lpr,nch,grid,unroll" overrides the choice (tuning runs);
+// an override that does not cover n is ignored.
 LsqrPlan make_lsqr_plan(const sns_matrix& A) {
   LsqrPlan p;
   const int es = A.dtype == SNS_F64 ? 8 : 4;
@@ -355,6 +521,20 @@ LsqrPlan make_lsqr_plan(const sns_matrix& A) {
   if (g > 1024) g = 1024;
   if (g < 1) g = 1;
   p.grid = (int)g;
+  p.unroll = 1;
+  if (const char* e = getenv("SNS_LSQR_PLAN")) {
+    int a = 0, b = 0, c = 0, d = 1;
+    if (sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d) >= 3) {
+      const bool lpr_ok = a == 4 || a == 8 || a == 16 || a == 32 || a == 64;
+      const bool nch_ok = b == 1 || b == 2 || b == 4 || b == 8;
+      if (lpr_ok && nch_ok && (int64_t)a * b * vw >= n && c >= 1 && c <= 65535) {
+        p.lpr = a;
+        p.nch = b;
+        p.grid = c;
+        p.unroll = d == 2 ? 2 : 1;
+      }
+    }
+  }
   return p;
 }
 
@@ -370,6 +550,11 @@ void carve_lsqr(Carve& c, const sns_matrix& A, const LsqrPlan& p, LsqrBufs& l) {
   l.u = c.take<char>((size_t)A.m * es);
   l.zpart = c.take<double>((size_t)p.grid * A.n);
   l.npart = c.take<double>((size_t)p.grid);
+  l.zred2 = c.take<double>((size_t)kRedSplit * A.n);
+  l.nred2 = c.take<double>((size_t)kRedSplit);
+  l.Xc = c.take<double>((size_t)A.n * A.n);
+  l.Xr = c.take<double>((size_t)A.n * A.n);
+  l.ypart = c.take<double>((size_t)(A.n + kGemvRows - 1) / kGemvRows);
   l.vecs = c.take<double>((size_t)6 * A.n);
   l.state = c.take<LsqrState>(1);
 }
@@ -413,17 +598,26 @@ sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan&
   double* v = l.vecs + n;
   double* wd = l.vecs + 2 * n;
   double* dy = l.vecs + 3 * n;
+  double* ybuf = l.vecs + 4 * n;
   LsqrState* st = static_cast<LsqrState*>(l.state);
   SNS_LAUNCH("lsqr_init", k_lsqr_init, dim3(1), dim3(256), 0, s, n, max_iters, stop, st, q.xw, wpass,
              dy);
-  const size_t lds_step = ((size_t)n + 4096 + 16 + 1024) * sizeof(double);
+  SNS_LAUNCH("tri_inv", k_tri_inv, dim3(n), dim3(kInvThreads), ((size_t)n + 4096) * sizeof(double),
+             s, n, q.R, q.invd, l.Xc, l.Xr);
+  const unsigned gemv_grid = (unsigned)((n + kGemvRows - 1) / kGemvRows);
+  const size_t lds_xtz = ((size_t)n + 16 + kGemvRows) * sizeof(double);
+  const size_t lds_xv = (size_t)n * sizeof(double);
   // iteration 0 is the residual pass r0 = b - A x0 plus the start-up step
   auto enqueue = [&](int it) {
     const void* uin = it == 0 ? b : l.u;
     if (A.dtype == SNS_F64) launch_pass_v<double, 2>(A, p, l, uin, s);
     else launch_pass_v<float, 4>(A, p, l, uin, s);
-    SNS_LAUNCH("lsqr_step", k_lsqr_step, dim3(1), dim3(1024), lds_step, s, n, p.grid, sighat, q.R,
-               l.zpart, l.npart, st, wpass, v, wd, dy);
+    SNS_LAUNCH("lsqr_reduce", k_lsqr_reduce, dim3((n + 63) / 64, kRedSplit), dim3(256), 0, s, n,
+               p.grid, st, l.zpart, l.npart, l.zred2, l.nred2);
+    SNS_LAUNCH("lsqr_xtz", k_lsqr_xtz, dim3(gemv_grid), dim3(kGemvThreads), lds_xtz, s, n, sighat,
+               l.Xc, l.zred2, l.nred2, st, nullptr, ybuf, l.ypart, v, wd, dy);
+    SNS_LAUNCH("lsqr_xv", k_lsqr_xv, dim3(gemv_grid), dim3(kGemvThreads), lds_xv, s, n, l.Xr, v,
+               static_cast<const double*>(nullptr), st, 1, wpass);
   };
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   SNS_HIP_TRY(hipStreamIsCapturing(s, &cap));
@@ -484,9 +678,10 @@ sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan&
       }
     }
   }
-  const size_t lds_fin = ((size_t)n + 4096) * sizeof(double);
-  SNS_LAUNCH("lsqr_final", k_lsqr_final, dim3(1), dim3(1024), lds_fin, s, n, q.R, q.xw, dy, st, x,
-             info_dev);
+  // x = x0 + X dy
+  SNS_LAUNCH("lsqr_final", k_lsqr_xv, dim3(gemv_grid), dim3(kGemvThreads), lds_xv, s, n, l.Xr, dy,
+             static_cast<const double*>(q.xw), st, 0, x);
+  SNS_LAUNCH("lsqr_report", k_lsqr_report, dim3(1), dim3(1), 0, s, st, info_dev);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }

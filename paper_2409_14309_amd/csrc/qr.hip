@@ -52,24 +52,23 @@ __device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t
                                            double* __restrict__ tau, double* __restrict__ flags) {
   const int64_t jk = j0 + K;  // pivot row, owned by thread K (r = 0)
   // partial sums over the rows below the pivot, x = column K there:
-  // G_c = x . M[:, c] (c >= K) and Y_a = x . V[:, a] (a < K)
+  // G_c = x . M[:, c] (c >= K) and Y_a = x . V[:, a] (a < K).  Rows at or
+  // above the pivot contribute x = 0; rows past d hold zeros.
   double g[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) g[c] = 0.0;
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
-    if (i > jk && i < d) {
-      const double x = P[r][K];
+    const double x = i > jk ? P[r][K] : 0.0;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) g[c] += x * P[r][c];
-    }
+    for (int c = 0; c < NB; ++c) g[c] = fma(x, P[r][c], g[c]);
   }
   if (t == K) {
 #pragma unroll
     for (int c = 0; c < NB; ++c) piv[c] = P[0][c];
   }
-  block_reduce_multi<NB>(g, red, tot);  // its barriers also publish piv
+  block_reduce_multi<NB, kPanelThreads>(g, red, tot);  // its barriers also publish piv
   const double alpha = piv[K];
   const double nu = sqrt(alpha * alpha + tot[K]);
   double beta = 0.0, tk = 0.0, scale = 0.0;
@@ -78,21 +77,21 @@ __device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t
     tk = (beta - alpha) / beta;
     scale = 1.0 / (alpha - beta);
   }
-  // apply H_K to the columns right of K: w_c = v . M[:, c] = piv[c] + scale G_c
+  // apply H_K = I - tau v v^T to the columns right of K:
+  // w_c = v . M[:, c] = piv[c] + scale G_c, M[i, c] -= tau v_i w_c with
+  // v_i = scale x_i below the pivot, 1 at the pivot, 0 above
+  double w[NB];
+#pragma unroll
+  for (int c = K + 1; c < NB; ++c) w[c] = piv[c] + scale * tot[c];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
-    if (i > jk && i < d) {
-      const double v = P[r][K] * scale;
-      P[r][K] = v;
+    const bool below = i > jk, at = i == jk;
+    const double v = P[r][K] * scale;
+    const double f = below ? tk * v : (at ? tk : 0.0);
 #pragma unroll
-      for (int c = K + 1; c < NB; ++c) P[r][c] -= tk * v * (piv[c] + scale * tot[c]);
-    }
-  }
-  if (t == K) {
-    P[0][K] = beta;
-#pragma unroll
-    for (int c = K + 1; c < NB; ++c) P[0][c] -= tk * (piv[c] + scale * tot[c]);
+    for (int c = K + 1; c < NB; ++c) P[r][c] = fma(-f, w[c], P[r][c]);
+    P[r][K] = below ? v : (at ? beta : P[r][K]);
   }
   // T[0:K, K] = -tau_K T[0:K, 0:K] (V[:, 0:K]^T v_K), with
   // V[:, a]^T v_K = piv[a] + scale Y_a; T[K, K] = tau_K
@@ -131,7 +130,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_qr_panel(int64_t d, int64_t j
                                                             double* __restrict__ tau,
                                                             double* __restrict__ Tg,
                                                             double* __restrict__ flags) {
-  __shared__ double red[(kPanelThreads / 64) * NB];
+  __shared__ double red[kPanelThreads * NB];
   __shared__ double tot[NB];
   __shared__ double piv[NB];
   __shared__ double Ts[NB * NB];
@@ -157,75 +156,78 @@ __global__ __launch_bounds__(kPanelThreads) void k_qr_panel(int64_t d, int64_t j
   for (int e = t; e < NB * NB; e += kPanelThreads) Tg[e] = Ts[e];
 }
 
-// C <- (I - V T V^T)^T C for the trailing columns [j0 + nbw, n] (Sb is the
-// last one), rows [j0, d).  Work-group = 256 threads = 32 row groups x 8
-// columns; W = V^T C is reduced over the row groups in a fixed order.
+// C <- (I - V T V^T)^T C = C - V (T^T (V^T C)) for the trailing columns
+// [j0 + nbw, n] (Sb is the last one), rows [j0, d).  A work-group owns CB
+// columns.  Sweep 1: every thread accumulates its rows' share of W = V^T C in
+// registers (independent loads, no barriers); W is reduced over the group
+// through LDS in a fixed order and multiplied by T^T.  Sweep 2 re-reads V and
+// C and applies the update.
+constexpr int kTrailThreads = 256;
+constexpr int kTrailCB = 4;
+
 template <int NB>
-__global__ __launch_bounds__(256) void k_qr_trailing(int64_t d, int64_t n, int64_t j0, int nbw,
-                                                     double* __restrict__ M,
-                                                     const double* __restrict__ Tg) {
-  constexpr int CB = 8, RG = 32;
-  __shared__ double Vt[RG][NB + 1];
-  __shared__ double Ws[NB][CB];
-  __shared__ double red[RG][NB][CB];
-  const int t = threadIdx.x, rg = t % RG, cl = t / RG;
-  const int64_t jc = j0 + nbw + (int64_t)blockIdx.x * CB + cl;
-  const bool colok = jc <= n;
-  double acc[NB];
+__device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t d, int64_t j0,
+                                          int a, int nbw, int64_t i) {
+  const int64_t ja = j0 + a;
+  if (a >= nbw) return 0.0;
+  return i > ja ? M[ja * d + i] : (i == ja ? 1.0 : 0.0);
+}
+
+template <int NB>
+__global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(int64_t d, int64_t n, int64_t j0,
+                                                               int nbw, double* __restrict__ M,
+                                                               const double* __restrict__ Tg) {
+  constexpr int CB = kTrailCB, NT = kTrailThreads, NV = NB * CB;
+  __shared__ double red[NV * NT];
+  __shared__ double W[NV];
+  __shared__ double Wt[NV];
+  const int t = threadIdx.x;
+  const int64_t jc0 = j0 + nbw + (int64_t)blockIdx.x * CB;
+  int64_t jc[CB];
+  bool ok[CB];
 #pragma unroll
-  for (int a = 0; a < NB; ++a) acc[a] = 0.0;
-  for (int64_t i0 = j0; i0 < d; i0 += RG) {
-    for (int e = t; e < RG * NB; e += 256) {
-      const int r = e % RG, a = e / RG;
-      const int64_t i = i0 + r, ja = j0 + a;
-      double v = 0.0;
-      if (a < nbw && i < d) v = i > ja ? M[ja * d + i] : (i == ja ? 1.0 : 0.0);
-      Vt[r][a] = v;
-    }
-    __syncthreads();
-    const int64_t i = i0 + rg;
-    if (colok && i < d) {
-      const double cv = M[jc * d + i];
-#pragma unroll
-      for (int a = 0; a < NB; ++a) acc[a] += Vt[rg][a] * cv;
-    }
-    __syncthreads();
+  for (int c = 0; c < CB; ++c) {
+    jc[c] = jc0 + c;
+    ok[c] = jc[c] <= n;
   }
+  double acc[NV];
 #pragma unroll
-  for (int a = 0; a < NB; ++a) red[rg][a][cl] = acc[a];
-  __syncthreads();
-  if (t < NB * CB) {
+  for (int e = 0; e < NV; ++e) acc[e] = 0.0;
+  for (int64_t i = j0 + t; i < d; i += NT) {
+    double v[NB], cv[CB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) v[a] = v_entry<NB>(M, d, j0, a, nbw, i);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) cv[c] = ok[c] ? M[jc[c] * d + i] : 0.0;
+#pragma unroll
+    for (int a = 0; a < NB; ++a)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[a * CB + c] = fma(v[a], cv[c], acc[a * CB + c]);
+  }
+  block_reduce_multi<NV, NT>(acc, red, W);
+  // W' = T^T W with T upper triangular (column-major NB x NB)
+  if (t < NV) {
     const int a = t / CB, c = t % CB;
     double s = 0.0;
-    for (int q = 0; q < RG; ++q) s += red[q][a][c];
-    red[0][a][c] = s;  // W[a][c]
+    for (int b2 = 0; b2 <= a && b2 < nbw; ++b2) s += Tg[a * NB + b2] * W[b2 * CB + c];
+    Wt[t] = a < nbw ? s : 0.0;
   }
   __syncthreads();
-  // W' = T^T W (T upper triangular)
-  if (t < NB * CB) {
-    const int a = t / CB, c = t % CB;
-    double s = 0.0;
-    for (int b = 0; b <= a && b < nbw; ++b) s += Tg[a * NB + b] * red[0][b][c];
-    Ws[a][c] = a < nbw ? s : 0.0;
-  }
-  __syncthreads();
-  for (int64_t i0 = j0; i0 < d; i0 += RG) {
-    for (int e = t; e < RG * NB; e += 256) {
-      const int r = e % RG, a = e / RG;
-      const int64_t i = i0 + r, ja = j0 + a;
-      double v = 0.0;
-      if (a < nbw && i < d) v = i > ja ? M[ja * d + i] : (i == ja ? 1.0 : 0.0);
-      Vt[r][a] = v;
-    }
-    __syncthreads();
-    const int64_t i = i0 + rg;
-    if (colok && i < d) {
+  double wt[NV];
+#pragma unroll
+  for (int e = 0; e < NV; ++e) wt[e] = Wt[e];
+  for (int64_t i = j0 + t; i < d; i += NT) {
+    double v[NB];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) v[a] = v_entry<NB>(M, d, j0, a, nbw, i);
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      if (!ok[c]) continue;
       double s = 0.0;
 #pragma unroll
-      for (int a = 0; a < NB; ++a) s += Vt[rg][a] * Ws[a][cl];
-      M[jc * d + i] -= s;
+      for (int a = 0; a < NB; ++a) s = fma(v[a], wt[a * CB + c], s);
+      M[jc[c] * d + i] -= s;
     }
-    __syncthreads();
   }
 }
 
@@ -234,6 +236,8 @@ __global__ __launch_bounds__(256) void k_qr_trailing(int64_t d, int64_t n, int64
 __global__ __launch_bounds__(1024) void k_qr_finish(int64_t d, int64_t n,
                                                     const double* __restrict__ M,
                                                     double* __restrict__ Rc,
+                                                    double* __restrict__ Rr,
+                                                    double* __restrict__ invd,
                                                     double* __restrict__ Rout,
                                                     double* __restrict__ x0,
                                                     double* __restrict__ flags,
@@ -253,8 +257,10 @@ __global__ __launch_bounds__(1024) void k_qr_finish(int64_t d, int64_t n,
     const int64_t j = e / n, i = e % n;  // Rc[j * n + i] = R[i, j]
     const double v = i <= j ? M[j * d + i] : 0.0;
     Rc[e] = v;
+    Rr[i * n + j] = v;
     if (Rout) Rout[i * n + j] = v;
   }
+  for (int64_t i = t; i < n; i += nt) invd[i] = 1.0 / M[i * d + i];
   double mx = 0.0;
   bool bad = false;
   for (int64_t i = t; i < n; i += nt) {
@@ -272,7 +278,7 @@ __global__ __launch_bounds__(1024) void k_qr_finish(int64_t d, int64_t n,
   for (int64_t i = t; i < n; i += nt) x[i] = M[n * d + i];
   __syncthreads();
   __syncthreads();
-  trsv_upper_lds(Rc, n, (int)n, x, blk);
+  trsv_lds<true, 1024>(Rc, n, (int)n, invd, x, blk);
   for (int64_t i = t; i < n; i += nt) x0[i] = x[i];
   if (t == 0) {
     flags[0] = rho;
@@ -298,7 +304,8 @@ void run_panels(int64_t d, int64_t n, const QrBufs& q, hipStream_t st) {
                        q.M, q.tau, q.T, q.scal);
     const int64_t ntr = n + 1 - (j0 + nbw);
     if (ntr > 0)
-      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB>), dim3((unsigned)((ntr + 7) / 8)), dim3(256), 0, st,
+      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB>), dim3((unsigned)((ntr + kTrailCB - 1) / kTrailCB)),
+                 dim3(kTrailThreads), 0, st,
                          d, n, j0, nbw, q.M, q.T);
   }
 }
@@ -317,6 +324,8 @@ void carve_qr(Carve& c, int64_t d, int64_t n, QrBufs& q) {
   q.T = c.take<double>(64 * 64);
   q.tau = c.take<double>((size_t)n);
   q.R = c.take<double>((size_t)n * n);
+  q.Rr = c.take<double>((size_t)n * n);
+  q.invd = c.take<double>((size_t)n);
   q.xw = c.take<double>((size_t)n);
   q.scal = c.take<double>(8);
 }
@@ -339,7 +348,8 @@ sns_status launch_qr_solve(int64_t d, int64_t n, sns_dtype dt, const void* SA, i
   else if (d <= 4096) run_panels<8, 8>(d, n, q, st);
   else run_panels<16, 4>(d, n, q, st);
   const size_t lds = ((size_t)n + 4096 + 16) * sizeof(double);
-  SNS_LAUNCH("qr_finish", k_qr_finish, dim3(1), dim3(1024), lds, st, d, n, q.M, q.R, Rout, x0, q.scal,
+  SNS_LAUNCH("qr_finish", k_qr_finish, dim3(1), dim3(1024), lds, st, d, n, q.M, q.R, q.Rr, q.invd,
+             Rout, x0, q.scal,
                      info_dev);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;

@@ -94,7 +94,7 @@ void timing_begin(const char* name, hipStream_t s) {
   t_pending.a = take_event(r);
   t_pending.b = take_event(r);
   if (!t_pending.a || !t_pending.b) return;
-  hipEventRecord(t_pending.a, s);
+  (void)hipEventRecord(t_pending.a, s);
   t_open = &t_pending;
 }
 
@@ -102,7 +102,7 @@ void timing_end(hipStream_t s) {
   if (!t_open) return;
   Registry& r = reg();
   std::lock_guard<std::mutex> g(r.mu);
-  hipEventRecord(t_open->b, s);
+  (void)hipEventRecord(t_open->b, s);
   r.recs.push_back(*t_open);
   t_open = nullptr;
   if (r.recs.size() > 4096) collect(r);
