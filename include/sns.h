@@ -85,9 +85,9 @@ typedef struct {
  *   lane = i & 1, h(i) = (w_{2 lane} * d) >> 32, s(i) = +1 if the top bit of
  *   w_{2 lane + 1} is clear, else -1.
  * Gaussian (Sec. 1.2.1): S = d^{-1/2} G with G[k, i] = T[q], q the byte
- *   (k & 15) of Philox4x32-10(counter (i mod 2^32, i >> 32, k >> 4, 1), key as
- *   above), T[q] = bf16(Phi^{-1}((q + 1/2) / 256)).  The product uses
- *   bf16(A) and bf16(b) (round to nearest even). */
+ *   (i & 15) of Philox4x32-10(counter (j mod 2^32, j >> 32, k, 1), key as
+ *   above), j = i >> 4, T[q] = bf16(Phi^{-1}((q + 1/2) / 256)).  The product
+ *   uses bf16(A) and bf16(b) (round to nearest even). */
 typedef struct {
   sns_sketch_kind kind;
   int64_t d;

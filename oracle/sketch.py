@@ -16,10 +16,12 @@ Readings fixed here (the paper is silent on them):
     multiply-shift reduction h = (w_h * d) >> 32 and the sign is +1 when the
     top bit of w_s is clear, else -1.  Entries of S are +-1 with no scale.
   * Gaussian sketch: entry G[k, i] is the table value T[q] where q is one
-    byte of Philox4x32-10 at counter (i mod 2^32, i >> 32, k >> 4, 1) and key
-    seed; byte (k & 15) of the little-endian 16-byte output.  T[q] is the
-    inverse normal CDF at the midpoint (q + 1/2) / 256 rounded to bfloat16
-    (round to nearest even).  SA = d^{-1/2} G bf16(A), Sb = d^{-1/2} G bf16(b).
+    byte of Philox4x32-10 at counter (j mod 2^32, j >> 32, k, 1), j = i >> 4,
+    and key seed: byte (i & 15) of the little-endian 16-byte output, so one
+    generator call serves 16 consecutive rows of A for one sketch row.  T[q]
+    is the inverse normal CDF at the midpoint (q + 1/2) / 256 rounded to
+    bfloat16 (round to nearest even).  SA = d^{-1/2} G bf16(A),
+    Sb = d^{-1/2} G bf16(b).
 """
 from __future__ import annotations
 
@@ -131,19 +133,27 @@ def gaussian_table() -> np.ndarray:
 
 def gaussian_codes(seed: int, d: int, i0: int, count: int) -> np.ndarray:
     """Byte codes q[k, i] (uint8, shape (d, count)) for columns i0..i0+count-1."""
-    i = np.uint64(i0) + np.arange(count, dtype=np.uint64)
-    c0 = (i & np.uint64(0xFFFFFFFF)).astype(np.uint32)
-    c1 = (i >> np.uint64(32)).astype(np.uint32)
-    nblk = (d + 15) // 16
-    q = np.empty((nblk * 16, count), dtype=np.uint8)
-    for kb in range(nblk):
-        c2 = np.full(count, kb, dtype=np.uint32)
-        c3 = np.full(count, TAG_GAUSS, dtype=np.uint32)
-        w = philox4x32(c0, c1, c2, c3, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
-        for t in range(4):
-            for byte in range(4):
-                q[16 * kb + 4 * t + byte, :] = ((w[t] >> np.uint32(8 * byte)) & np.uint32(0xFF)).astype(np.uint8)
-    return q[:d, :]
+    if count == 0:
+        return np.zeros((d, 0), dtype=np.uint8)
+    j0 = i0 >> 4
+    j1 = (i0 + count - 1) >> 4
+    nb = j1 - j0 + 1
+    jj = np.uint64(j0) + np.arange(nb, dtype=np.uint64)
+    kk = np.arange(d, dtype=np.uint32)
+    J = np.repeat(jj, d)                 # block-major: (block, k)
+    K = np.tile(kk, nb)
+    c0 = (J & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    c1 = (J >> np.uint64(32)).astype(np.uint32)
+    c3 = np.full(J.shape, TAG_GAUSS, dtype=np.uint32)
+    w = philox4x32(c0, c1, K, c3, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    # bytes of (w0, w1, w2, w3), little-endian: byte b is column 16 j + b
+    by = np.stack(w, axis=1).astype(np.uint32)            # (nb * d, 4)
+    shifts = np.array([0, 8, 16, 24], dtype=np.uint32)
+    q = ((by[:, :, None] >> shifts[None, None, :]) & np.uint32(0xFF)).astype(np.uint8)
+    q = q.reshape(nb, d, 16)                              # (block, k, byte)
+    full = np.transpose(q, (1, 0, 2)).reshape(d, nb * 16)  # columns 16 j0 .. 16 j1 + 15
+    off = i0 - 16 * j0
+    return np.ascontiguousarray(full[:, off:off + count])
 
 
 def gaussian_matrix(seed: int, d: int, m: int, i0: int = 0) -> np.ndarray:
