@@ -131,15 +131,17 @@ def gaussian_table() -> np.ndarray:
     return bf16_round(ndtri((q + 0.5) / 256.0))
 
 
-def gaussian_codes(seed: int, d: int, i0: int, count: int) -> np.ndarray:
-    """Byte codes q[k, i] (uint8, shape (d, count)) for columns i0..i0+count-1."""
+def gaussian_codes(seed: int, d: int, i0: int, count: int, rows=None) -> np.ndarray:
+    """Byte codes q[k, i] (uint8, shape (d, count)) for columns i0..i0+count-1;
+    with `rows` given, only those sketch rows k (shape (len(rows), count))."""
+    kk = np.arange(d, dtype=np.uint32) if rows is None else np.asarray(rows, dtype=np.uint32)
+    d = kk.size
     if count == 0:
         return np.zeros((d, 0), dtype=np.uint8)
     j0 = i0 >> 4
     j1 = (i0 + count - 1) >> 4
     nb = j1 - j0 + 1
     jj = np.uint64(j0) + np.arange(nb, dtype=np.uint64)
-    kk = np.arange(d, dtype=np.uint32)
     J = np.repeat(jj, d)                 # block-major: (block, k)
     K = np.tile(kk, nb)
     c0 = (J & np.uint64(0xFFFFFFFF)).astype(np.uint32)
@@ -156,9 +158,10 @@ def gaussian_codes(seed: int, d: int, i0: int, count: int) -> np.ndarray:
     return np.ascontiguousarray(full[:, off:off + count])
 
 
-def gaussian_matrix(seed: int, d: int, m: int, i0: int = 0) -> np.ndarray:
-    """G[k, i] for i in [i0, i0+m) (unscaled, float64, shape (d, m))."""
-    return gaussian_table()[gaussian_codes(seed, d, i0, m)]
+def gaussian_matrix(seed: int, d: int, m: int, i0: int = 0, rows=None) -> np.ndarray:
+    """G[k, i] for i in [i0, i0+m) (unscaled, float64, shape (d, m)); with
+    `rows`, only those sketch rows."""
+    return gaussian_table()[gaussian_codes(seed, d, i0, m, rows)]
 
 
 def gaussian_apply(A, b, seed: int, d: int):

@@ -68,6 +68,7 @@ sns_status run_sketch(const sns_sketch& sk, const sns_matrix& A, const void* b, 
 
 struct LstsqWs {
   SketchWs sw;
+  void* gauss = nullptr;  // Gaussian sketch partials
   void* SA = nullptr;
   void* Sb = nullptr;
   QrBufs q{};
@@ -78,7 +79,8 @@ struct LstsqWs {
 
 void carve_lstsq(Carve& c, const sns_sketch& sk, const sns_matrix& A, const sns_solve_opts& o,
                  LstsqWs& w) {
-  carve_sketch(c, sk, A, true, o.accum_fp64 != 0, w.sw);
+  if (sk.kind == SNS_SKETCH_GAUSSIAN) w.gauss = c.take<char>(gauss_workspace_bytes(A, (uint32_t)sk.d));
+  else carve_sketch(c, sk, A, true, o.accum_fp64 != 0, w.sw);
   w.SA = c.take<char>((size_t)sk.d * A.n * elem(A));
   w.Sb = c.take<char>((size_t)sk.d * elem(A));
   carve_qr(c, sk.d, A.n, w.q);
@@ -200,8 +202,7 @@ sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
   Carve c(nullptr, 0);
   LstsqWs w;
   carve_lstsq(c, *sk, *A, o, w);
-  size_t extra = sk->kind == SNS_SKETCH_GAUSSIAN ? gauss_workspace_bytes(*A, (uint32_t)sk->d) : 0;
-  *bytes = c.off + align_up(extra);
+  *bytes = c.off;
   return SNS_OK;
 }
 
@@ -221,12 +222,10 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   Carve c(workspace, ws_bytes);
   LstsqWs w;
   carve_lstsq(c, *sk, *A, o, w);
-  void* gws = nullptr;
-  if (sk->kind == SNS_SKETCH_GAUSSIAN) gws = c.take<char>(gauss_workspace_bytes(*A, (uint32_t)sk->d));
   if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
   hipStream_t st = (hipStream_t)stream;
   if (sk->kind == SNS_SKETCH_GAUSSIAN)
-    s = launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, gws, st);
+    s = launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, w.gauss, st);
   else
     s = run_sketch(*sk, *A, b, w.SA, w.Sb, w.sw, st);
   if (s != SNS_OK) return s;

@@ -1,11 +1,17 @@
 // Dense Gaussian sketch (Gaussian operator, i.i.d. normal entries):
 // SA = d^{-1/2} G bf16(A), Sb = d^{-1/2} G bf16(b), on the matrix cores.
 //
-// G[k, i] = T[q] with q the byte (k & 15) of Philox4x32-10 at counter
-// (i mod 2^32, i >> 32, k >> 4, 1) and the sketch seed as key; T[q] is the
+// G[k, i] = T[q] with q the byte (i & 15) of Philox4x32-10 at counter
+// (i >> 4 mod 2^32, i >> 36, k, 1) and the sketch seed as key; T[q] is the
 // normal quantile at (q + 1/2) / 256 rounded to bfloat16.  The table is built
 // here on the host from the complementary error function by bisection and
 // rounded to bfloat16 directly from the double's bits (ties to even).
+//
+// The product is a split-K GEMM on the matrix cores: G is generated per
+// K-step into LDS (one Philox call per thread), A is converted to bf16 into
+// LDS, and each work-group accumulates its 128 x 256 tile of SA over a chunk
+// of rows in fp32; a second kernel adds the chunks in a fixed order and
+// applies d^{-1/2}.
 #include <math.h>
 #include <mutex>
 #include <string.h>
@@ -59,16 +65,246 @@ const uint16_t* gauss_table_host() {
   return g_table;
 }
 
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+// Tile of one work-group: 128 sketch rows x 256 columns of SA, fed by K-steps
+// of 32 rows of A.  Four waves: wave (wr, wc) owns rows [64 wr, 64 wr + 64)
+// and columns [128 wc, 128 wc + 128) as 2 x 4 tiles of 32 x 32 computed with
+// v_mfma_f32_32x32x16_bf16 (two k-substeps of 16 per K-step).
+constexpr int kTM = 128, kTN = 256, kKS = 32, kThreads = 256;
+constexpr int kPad = 40;  // LDS row stride in bf16: 32 values + 8 (keeps 16-byte reads conflict free)
+
+struct GaussTable {
+  uint32_t w[128];  // T[2e] in the low half, T[2e + 1] in the high half
+};
+
+__device__ __forceinline__ __bf16 bits_to_bf16(unsigned short u) {
+  return __builtin_bit_cast(__bf16, u);
+}
+
+// SA partials (split K): partA[kc][k][j] = sum over this chunk's rows i of
+// G[k, i] bf16(A[i, j]) (fp32 accumulation on the matrix cores), and
+// partB[kc][k] = sum G[k, i] bf16(b[i]) (fp32 on the vector units).
+// G[k, i] = T[q], q = byte (i & 15) of Philox4x32-10 at counter
+// (i >> 4, 0, k, 1) (high counter word: i >> 36), key = seed.
+__global__ __launch_bounds__(kThreads, 2) void k_gauss_sketch(
+    const float* __restrict__ A, int64_t ld, int64_t m, int n, const float* __restrict__ b,
+    uint64_t seed, int d, GaussTable table, int64_t ksteps, int vec_ok, float* __restrict__ partA,
+    float* __restrict__ partB) {
+  __shared__ unsigned short tbl[256];
+  __shared__ __attribute__((aligned(16))) unsigned short Gbuf[2][kTM * kPad];
+  __shared__ __attribute__((aligned(16))) unsigned short Bbuf[2][kTN * kPad];
+  __shared__ float sbred[2][kTM];
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int k0 = blockIdx.x * kTM, j0 = blockIdx.y * kTN, kc = blockIdx.z, S = gridDim.z;
+  const int64_t s0 = ksteps * kc / S, s1 = ksteps * (kc + 1) / S;
+  if (t < 128) {
+    tbl[2 * t] = (unsigned short)(table.w[t] & 0xFFFFu);
+    tbl[2 * t + 1] = (unsigned short)(table.w[t] >> 16);
+  }
+  // generator role: sketch row r, half h (16 consecutive rows of A)
+  const int gr = t & 127, gh = t >> 7;
+  const int gk = k0 + gr;
+  const bool do_b = b != nullptr && blockIdx.y == 0;
+  float sb = 0.f;
+  // A-loading role: 4 columns (4 ac .. 4 ac + 3), 8 rows (8 ar .. 8 ar + 7)
+  const int ac = t & 63, ar = t >> 6;
+  const int aj = j0 + 4 * ac;
+
+  f32x16 acc[2][4];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[rt][ct][q] = 0.f;
+
+  float av[8][4];
+  auto load_A = [&](int64_t st) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t i = st * kKS + 8 * ar + e;
+      if (i < m && vec_ok && aj + 3 < n) {
+        const float4 x = *reinterpret_cast<const float4*>(A + i * ld + aj);
+        av[e][0] = x.x; av[e][1] = x.y; av[e][2] = x.z; av[e][3] = x.w;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) av[e][c] = (i < m && aj + c < n) ? A[i * ld + aj + c] : 0.f;
+      }
+    }
+  };
+  auto store_A = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      bf16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = (__bf16)av[e][c];
+      *reinterpret_cast<bf16x8*>(&Bbuf[buf][(4 * ac + c) * kPad + 8 * ar]) = v;
+    }
+  };
+  auto gen_G = [&](int64_t st, int buf) {
+    const uint64_t jb = (uint64_t)(st * kKS) / 16 + gh;  // 16-row block of A
+    bf16x8 lo, hi;
+    if (gk < d) {
+      const U4 w = philox4x32_10(U4{(uint32_t)jb, (uint32_t)(jb >> 32), (uint32_t)gk, 1u},
+                                 (uint32_t)seed, (uint32_t)(seed >> 32));
+      const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const unsigned short g = tbl[(wv[e >> 2] >> (8 * (e & 3))) & 0xFFu];
+        if (e < 8) lo[e] = bits_to_bf16(g);
+        else hi[e - 8] = bits_to_bf16(g);
+      }
+      if (do_b) {
+        const int64_t ib = (int64_t)jb * 16;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int64_t i = ib + e;
+          const float bv = i < m ? (float)(__bf16)b[i] : 0.f;
+          sb = fmaf((float)(e < 8 ? lo[e] : hi[e - 8]), bv, sb);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) { lo[e] = (__bf16)0.f; hi[e] = (__bf16)0.f; }
+    }
+    *reinterpret_cast<bf16x8*>(&Gbuf[buf][gr * kPad + 16 * gh]) = lo;
+    *reinterpret_cast<bf16x8*>(&Gbuf[buf][gr * kPad + 16 * gh + 8]) = hi;
+  };
+  auto mfma = [&](int buf) {
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int kofs = 16 * ks + 8 * (lane >> 5);
+      bf16x8 ao[2], bo[4];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+        ao[rt] = *reinterpret_cast<const bf16x8*>(
+            &Gbuf[buf][(wr * 64 + rt * 32 + (lane & 31)) * kPad + kofs]);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        bo[ct] = *reinterpret_cast<const bf16x8*>(
+            &Bbuf[buf][(wc * 128 + ct * 32 + (lane & 31)) * kPad + kofs]);
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct)
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ao[rt], bo[ct], acc[rt][ct], 0, 0, 0);
+    }
+  };
+
+  __syncthreads();  // table ready
+  if (s0 < s1) {
+    load_A(s0);
+    gen_G(s0, 0);
+    store_A(0);
+    __syncthreads();
+    for (int64_t st = s0; st < s1; ++st) {
+      const int cur = (int)((st - s0) & 1), nxt = cur ^ 1;
+      const bool more = st + 1 < s1;
+      if (more) load_A(st + 1);
+      mfma(cur);
+      if (more) {
+        gen_G(st + 1, nxt);
+        store_A(nxt);
+      }
+      __syncthreads();
+    }
+  }
+  // epilogue: accumulator element q of lane l in a 32 x 32 tile is
+  // row 8 (q / 4) + 4 (l / 32) + q % 4, column l % 32
+  float* P = partA + (size_t)kc * d * n;
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const int col = j0 + wc * 128 + ct * 32 + (lane & 31);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int row = k0 + wr * 64 + rt * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        if (row < d && col < n) P[(size_t)row * n + col] = acc[rt][ct][q];
+      }
+    }
+  if (do_b) {
+    sbred[gh][gr] = sb;
+    __syncthreads();
+    if (t < kTM && k0 + t < d) partB[(size_t)kc * d + k0 + t] = sbred[0][t] + sbred[1][t];
+  }
+}
+
+// SA = scale * sum_kc partA[kc], Sb = scale * sum_kc partB[kc] (chunks in order).
+__global__ void k_gauss_reduce(int64_t dn, int d, int S, float scale, const float* __restrict__ partA,
+                               const float* __restrict__ partB, float* __restrict__ SA,
+                               float* __restrict__ Sb) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < dn + d;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < dn) {
+      float s = 0.f;
+      for (int c = 0; c < S; ++c) s += partA[(size_t)c * dn + e];
+      SA[e] = s * scale;
+    } else if (Sb) {
+      const int64_t k = e - dn;
+      float s = 0.f;
+      for (int c = 0; c < S; ++c) s += partB[(size_t)c * d + k];
+      Sb[k] = s * scale;
+    }
+  }
+}
+
+struct GaussPlan {
+  int mt, nt, S;
+  int64_t ksteps;
+};
+
+GaussPlan make_gauss_plan(const sns_matrix& A, uint32_t d) {
+  GaussPlan g;
+  g.mt = (int)((d + kTM - 1) / kTM);
+  g.nt = (int)((A.n + kTN - 1) / kTN);
+  g.ksteps = (A.m + kKS - 1) / kKS;
+  const int64_t tiles = (int64_t)g.mt * g.nt;
+  int64_t S = (512 + tiles - 1) / tiles;        // about two work-groups per CU
+  const int64_t maxS = g.ksteps / 8 > 0 ? g.ksteps / 8 : 1;  // >= 8 K-steps per chunk
+  if (S > maxS) S = maxS;
+  if (S > 256) S = 256;
+  if (S < 1) S = 1;
+  g.S = (int)S;
+  return g;
+}
+
+}  // namespace
+
 size_t gauss_workspace_bytes(const sns_matrix& A, uint32_t d) {
-  (void)A;
-  (void)d;
-  return 256;
+  const GaussPlan g = make_gauss_plan(A, d);
+  return align_up((size_t)g.S * d * A.n * sizeof(float)) + align_up((size_t)g.S * d * sizeof(float));
 }
 
 sns_status launch_gauss_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
                                void* SA, void* Sb, void* ws, hipStream_t st) {
-  (void)A; (void)d; (void)seed; (void)b; (void)SA; (void)Sb; (void)ws; (void)st;
-  return SNS_ERR_DTYPE;
+  if (A.dtype != SNS_F32 || A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+  const GaussPlan g = make_gauss_plan(A, d);
+  float* partA = static_cast<float*>(ws);
+  float* partB = reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                          align_up((size_t)g.S * d * A.n * sizeof(float)));
+  GaussTable tab;
+  const uint16_t* T = gauss_table_host();
+  for (int e = 0; e < 128; ++e) tab.w[e] = (uint32_t)T[2 * e] | ((uint32_t)T[2 * e + 1] << 16);
+  const int vec_ok = ((uintptr_t)A.values % 16 == 0) && (A.ld % 4 == 0);
+  SNS_LAUNCH("gauss_mfma", k_gauss_sketch, dim3(g.mt, g.nt, g.S), dim3(kThreads), 0, st,
+             static_cast<const float*>(A.values), A.ld, A.m, (int)A.n,
+             static_cast<const float*>(b), seed, (int)d, tab, g.ksteps, vec_ok, partA, partB);
+  const int64_t dn = (int64_t)d * A.n;
+  int64_t blocks = (dn + d + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  const float scale = (float)(1.0 / sqrt((double)d));
+  SNS_LAUNCH("gauss_reduce", k_gauss_reduce, dim3((unsigned)blocks), dim3(256), 0, st, dn, (int)d,
+             g.S, scale, partA, b ? partB : nullptr, static_cast<float*>(SA),
+             b ? static_cast<float*>(Sb) : nullptr);
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
 }
 
 }  // namespace sns
