@@ -6,7 +6,9 @@ workload (A 4,194,304 x 256, sigma log-spaced 1 .. 1e-6, relative noise 1e-4):
 CountSketch of [A | b] with d = 1024 (bucket sort + segmented reduction), FP64
 Householder QR of [SA | Sb], triangular solve, then R^{-1}-preconditioned LSQR
 on the full A until the device stop rule certifies residual error <= 1e-6.
-Inputs are resident in HBM before timing starts.
+Inputs are resident in HBM before timing starts.  --workload
+gauss_bf16_262144x512 times the same solve with the dense Gaussian sketch
+(d = 2048, bf16 MFMA) of a 262,144 x 512 column-scaled matrix instead.
 
 Prints one JSON line: solves/s (value), p50/p99 step latency, the CountSketch
 pass bandwidth, a roofline record for the dominant kernel (timed with HIP
@@ -29,7 +31,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CountSketch HBM GB/s (% peak); LS solves/s + p99 latency at rel-residual 1e-6"
 HBM_PEAK_GBPS = 8000.0
-WORKLOAD = "illcond_fp32_4194304x256"
+BF16_PEAK_TFLOPS = 2500.0
+# name -> (generator, m, n, d, sketch, data description)
+WORKLOADS = {
+    "illcond_fp32_4194304x256": ("dense_ill_conditioned", 4194304, 256, 1024, "count",
+                                 "synthetic (seeded; A = G diag(sigma) V^T, kappa 1e6)"),
+    "gauss_bf16_262144x512": ("dense_scaled_columns", 262144, 512, 2048, "gaussian",
+                              "synthetic (seeded; N(0,1) columns scaled 1 .. 1e-3)"),
+}
 
 
 def log(msg):
@@ -57,14 +66,14 @@ def measured_traffic(kernel: str, src_hash: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(A, b, d, rtol, rows, full_m):
+def cpu_baseline(A, b, d, rtol, rows, full_m, kind):
     """The oracle (unchanged) on the first `rows` rows, scaled to full m."""
     from threadpoolctl import threadpool_info
 
     from oracle import solve as OSV
     As, bs = A[:rows], b[:rows]
     t0 = time.perf_counter()
-    r = OSV.sap_sas(As, bs, "count", 42, d, 100, rtol=rtol)
+    r = OSV.sap_sas(As, bs, kind, 42, d, 100, rtol=rtol)
     dt = time.perf_counter() - t0
     est = dt * (full_m / rows)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
@@ -79,9 +88,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--m", type=int, default=4194304)
-    ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--d", type=int, default=1024)
+    ap.add_argument("--workload", default="illcond_fp32_4194304x256", choices=sorted(WORKLOADS))
+    ap.add_argument("--m", type=int, default=0, help="override the workload's row count")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--max-iters", type=int, default=80)
     ap.add_argument("--cpu-rows", type=int, default=1 << 19)
@@ -96,23 +104,26 @@ def main():
     import torch
 
     import paper_2409_14309_amd as sns
-    from workloads import dense_ill_conditioned
+    import workloads
 
     sns.load()
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    m, n, d = args.m, args.n, args.d
-    log(f"generating A {m}x{n} fp32 (kappa 1e6) ...")
+    gen, m, n, d, kind, data_desc = WORKLOADS[args.workload]
+    if args.m:
+        m = args.m
+    seed = 1001 if kind == "count" else 1003
+    log(f"generating {args.workload}: A {m}x{n} fp32 ...")
     t0 = time.time()
-    p = dense_ill_conditioned(m, n, seed=1001)
+    p = getattr(workloads, gen)(m, n, seed=seed)
     log(f"generated in {time.time() - t0:.1f}s; copying to HBM")
     dev = torch.device("cuda:0")
     A = torch.from_numpy(p.A).to(dev)
     b = torch.from_numpy(p.b).to(dev)
     torch.cuda.synchronize()
 
-    sk = sns.sketch_desc("count", d, 42)
+    sk = sns.sketch_desc(kind, d, 42)
     M = sns.dense(A)
     o = sns.opts(refine=1, max_iters=args.max_iters, rtol=args.rtol)
     ws = torch.empty(sns.sns_lstsq_workspace_size(sk, M, o), dtype=torch.uint8, device=dev)
@@ -163,15 +174,28 @@ def main():
         # CountSketch: A and b once, SA and Sb written
         "cs_gather": 4.0 * m * (n + 1) + 4.0 * d * (n + 1),
     }
-    src = {"lsqr_pass": ("lsqr.hip",), "cs_gather": ("countsketch.hip",)}
-    roof = None
-    if dom in bytes_per:
-        cnt, tot, avg_us = kt[dom]
-        ach = bytes_per[dom] / (avg_us * 1e-6) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
-                "traffic": measured_traffic(dom, kernel_source_hash(*src[dom])),
-                "bytes_per_launch": bytes_per[dom], "avg_launch_us": avg_us, "launches": cnt}
+    # Gaussian sketch: 2 d m n flops for G A plus 2 d m for G b
+    flops_per = {"gauss_mfma": 2.0 * d * m * n + 2.0 * d * m}
+    src = {"lsqr_pass": ("lsqr.hip",), "cs_gather": ("countsketch.hip",), "gauss_mfma": ("gauss.hip",)}
+
+    def roofline(kname):
+        cnt, tot, avg_us = kt[kname]
+        if kname in bytes_per:
+            ach = bytes_per[kname] / (avg_us * 1e-6) / 1e9
+            return {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                    "traffic": measured_traffic(kname, kernel_source_hash(*src[kname])),
+                    "bytes_per_launch": bytes_per[kname], "avg_launch_us": avg_us, "launches": cnt}
+        if kname in flops_per:
+            ach = flops_per[kname] / (avg_us * 1e-6) / 1e12
+            return {"kernel": kname, "bound": "mfma", "achieved": round(ach, 1),
+                    "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
+                    "flops_per_launch": flops_per[kname], "avg_launch_us": avg_us, "launches": cnt}
+        return None
+
+    roof = roofline(dom)
+    gauss = roofline("gauss_mfma") if "gauss_mfma" in kt else None
     cs = kt.get("cs_gather")
     sort_us = sum(kt[k][2] for k in ("sort_count", "scan_segments", "scan_buckets", "sort_scatter")
                   if k in kt)
@@ -186,7 +210,7 @@ def main():
     if not args.no_cpu:
         rows = min(args.cpu_rows, m)
         log(f"timing the CPU oracle on {rows} rows ...")
-        cpu = cpu_baseline(p.A, p.b, d, args.rtol, rows, m)
+        cpu = cpu_baseline(p.A, p.b, d, args.rtol, rows, m, kind)
         log(f"oracle sample took {cpu['seconds_sample']:.2f}s")
 
     out = {
@@ -200,9 +224,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 storage, f64 accumulation (QR and LSQR in f64)",
-        "data": "synthetic (seeded; A = G diag(sigma) V^T, kappa 1e6)",
-        "config": {"workload": WORKLOAD, "m": m, "n": n, "d": d, "sketch": "countsketch",
+        "dtype": ("f32 storage, f64 accumulation (QR and LSQR in f64)" if kind == "count" else
+                  "bf16 x bf16 -> f32 sketch on MFMA; f32 storage, f64 accumulation (QR, LSQR)"),
+        "data": data_desc,
+        "config": {"workload": args.workload, "m": m, "n": n, "d": d,
+                   "sketch": "countsketch" if kind == "count" else "gaussian",
                    "solver": "SAP-SAS (sketch, Householder QR, LSQR on A R^-1)",
                    "rtol": args.rtol, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
@@ -211,6 +237,7 @@ def main():
         "status": statuses,
         "rel_resid_est": max(ests) if ests else None,
         "countsketch": countsketch,
+        "gaussian_sketch": gauss,
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_us": round(v[2], 3)}
                     for k, v in kt.items()},

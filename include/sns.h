@@ -65,8 +65,13 @@ typedef enum {
 } sns_sketch_kind;
 
 /* A tall matrix.  Dense: values (m x n row-major, leading dimension ld).
- * CSR: row_ptr[m+1] and col_idx[nnz] (int32, column indices ascending within a
- * row), values[nnz]; ld is ignored.  `values` has the element type `dtype`. */
+ * CSR: row_ptr[m+1] (int32, nondecreasing, row_ptr[0] = 0, row_ptr[m] = nnz),
+ * col_idx[nnz] (int32, each in [0, n), no repeated column within a row) and
+ * values[nnz], all in device memory (col_idx and values may be NULL when
+ * nnz = 0); ld is ignored.  The library does not
+ * read these arrays on the host: entries with a column outside [0, n) are
+ * ignored, and row_ptr values outside [0, nnz] are undefined behaviour.
+ * `values` has the element type `dtype`. */
 typedef struct {
   int64_t m, n;
   sns_dtype dtype;
@@ -135,11 +140,15 @@ sns_status sns_sketch_workspace_size(const sns_sketch* sk, const sns_matrix* A, 
  * CountSketch: one deterministic pass over [A | b]; rows are grouped by bucket
  * with a stable counting sort and each bucket is reduced in a fixed order.
  * accum_fp64 (from opts, may be NULL) selects fp64 accumulation for fp32 A.
- * Gaussian: fp32 A only (SNS_ERR_DTYPE otherwise); computed on the matrix
- * cores as bf16 x bf16 products with fp32 accumulation.
+ * CSR A (CountSketch only): the rows that hold nonzeros are compacted and
+ * sorted by bucket the same way, each bucket adds its rows' nonzeros in
+ * ascending row order; Sb is formed over all m rows.  Requires n <= 4096.
+ * Gaussian: fp32 dense A only (SNS_ERR_DTYPE otherwise); computed on the
+ * matrix cores as bf16 x bf16 products with fp32 accumulation.
  * Errors: SNS_ERR_INVALID_ARG (NULL sk/A/SA/workspace, b and Sb not both set
- * or both NULL), SNS_ERR_SHAPE (n < 1, d < 1, m < 1, ld < n, m >= 2^31),
- * SNS_ERR_OUT_OF_MEMORY (ws_bytes too small). */
+ * or both NULL), SNS_ERR_SHAPE (n < 1, d < 1, m < 1, ld < n, m >= 2^31,
+ * d > 16384, d < n, d > m, CSR with n > 4096), SNS_ERR_OUT_OF_MEMORY
+ * (ws_bytes too small). */
 sns_status sns_sketch_apply(const sns_sketch* sk, const sns_matrix* A, const void* b,
                             void* SA, void* Sb, const sns_solve_opts* opts,
                             void* workspace, size_t ws_bytes, void* stream);
@@ -169,6 +178,8 @@ sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
  * b: device, m entries of A's dtype.  x: device fp64[n].
  * info: HOST pointer (pinned memory recommended) or NULL; written on the
  * stream, valid after synchronising it.
+ * A may be CSR with refine = 0 (plain sketch-and-solve); refinement streams
+ * dense rows and returns SNS_ERR_DTYPE for CSR.
  * Errors: as sns_sketch_apply, plus SNS_ERR_INVALID_ARG for max_iters < 0 or
  * rtol < 0. */
 sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, double* x,

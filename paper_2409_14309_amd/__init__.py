@@ -15,6 +15,22 @@ from ._binding import (SNS_CSR, SNS_DENSE_ROWMAJOR, SNS_F32, SNS_F64, SNS_SKETCH
                        sns_timing_summary, sns_version)
 
 
+class CsrMatrix:
+    """A CSR matrix held in device tensors: row_ptr int32[m+1], col_idx
+    int32[nnz] (distinct columns within a row), values float32/float64[nnz]."""
+
+    def __init__(self, row_ptr, col_idx, values, shape):
+        self.row_ptr, self.col_idx, self.values = row_ptr, col_idx, values
+        self.shape = (int(shape[0]), int(shape[1]))
+        self.dtype, self.device = values.dtype, values.device
+
+
+def _describe(A) -> Matrix:
+    if isinstance(A, CsrMatrix):
+        return csr(A.row_ptr, A.col_idx, A.values, A.shape[0], A.shape[1])
+    return dense(A)
+
+
 def _workspace(nbytes: int, device):
     import torch
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
@@ -22,10 +38,11 @@ def _workspace(nbytes: int, device):
 
 def sketch(A, b=None, kind: str = "count", d: int = None, seed: int = 42, accum_fp64: bool = False,
            stream=None):
-    """SA, Sb = S A, S b for a dense device tensor A (and optional b)."""
+    """SA, Sb = S A, S b for a dense device tensor or a CsrMatrix A (and
+    optional b)."""
     import torch
     sk = sketch_desc(kind, d, seed)
-    M = dense(A)
+    M = _describe(A)
     ws = _workspace(sns_sketch_workspace_size(sk, M), A.device)
     SA = torch.empty((d, A.shape[1]), dtype=A.dtype, device=A.device)
     Sb = torch.empty(d, dtype=A.dtype, device=A.device) if b is not None else None
@@ -38,7 +55,7 @@ def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine: bool
     """x (float64 device tensor) and Info for min ||A x - b||."""
     import torch
     sk = sketch_desc(kind, d, seed)
-    M = dense(A)
+    M = _describe(A)
     o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0, int(accum_fp64))
     ws = _workspace(sns_lstsq_workspace_size(sk, M, o), A.device)
     x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)

@@ -13,16 +13,20 @@ namespace {
 constexpr int64_t kMaxRows = (int64_t(1) << 31) - 1;  // row ids fit 31 bits
 constexpr int64_t kMaxD = 16384;      // CountSketch bucket sort (LDS histograms)
 constexpr int64_t kMaxQrD = 8192;     // register-resident QR panels
+constexpr int64_t kMaxCsrN = 4096;    // CSR sketch: one output row per wave in LDS
 
 sns_status check_matrix(const sns_matrix* A) {
-  if (!A || !A->values) return SNS_ERR_INVALID_ARG;
+  if (!A) return SNS_ERR_INVALID_ARG;
+  // a CSR matrix without nonzeros may leave values and col_idx NULL
+  const bool empty_csr = A->layout == SNS_CSR && A->nnz == 0;
+  if (!A->values && !empty_csr) return SNS_ERR_INVALID_ARG;
   if (A->dtype != SNS_F32 && A->dtype != SNS_F64) return SNS_ERR_DTYPE;
   if (A->layout != SNS_DENSE_ROWMAJOR && A->layout != SNS_CSR) return SNS_ERR_DTYPE;
   if (A->m < 1 || A->n < 1 || A->m > kMaxRows) return SNS_ERR_SHAPE;
   if (A->layout == SNS_DENSE_ROWMAJOR && A->ld < A->n) return SNS_ERR_SHAPE;
   if (A->layout == SNS_CSR) {
-    if (!A->row_ptr || !A->col_idx) return SNS_ERR_INVALID_ARG;
-    if (A->nnz < 0 || A->nnz > kMaxRows) return SNS_ERR_SHAPE;
+    if (!A->row_ptr || (!A->col_idx && !empty_csr)) return SNS_ERR_INVALID_ARG;
+    if (A->nnz < 0 || A->nnz > kMaxRows - 128) return SNS_ERR_SHAPE;
   }
   return SNS_OK;
 }
@@ -35,7 +39,7 @@ sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A) {
     if (sk->d < A->n || sk->d > A->m) return SNS_ERR_SHAPE;
     if (sk->kind == SNS_SKETCH_GAUSSIAN && A->dtype != SNS_F32) return SNS_ERR_DTYPE;
     if (sk->kind == SNS_SKETCH_GAUSSIAN && A->layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
-    if (sk->kind == SNS_SKETCH_COUNT && A->layout == SNS_CSR) return SNS_ERR_DTYPE;
+    if (sk->kind == SNS_SKETCH_COUNT && A->layout == SNS_CSR && A->n > kMaxCsrN) return SNS_ERR_SHAPE;
   }
   return SNS_OK;
 }
@@ -69,6 +73,8 @@ sns_status run_sketch(const sns_sketch& sk, const sns_matrix& A, const void* b, 
 struct LstsqWs {
   SketchWs sw;
   void* gauss = nullptr;  // Gaussian sketch partials
+  void* csr = nullptr;    // CSR sketch workspace
+  size_t csr_bytes = 0;
   void* SA = nullptr;
   void* Sb = nullptr;
   QrBufs q{};
@@ -79,8 +85,14 @@ struct LstsqWs {
 
 void carve_lstsq(Carve& c, const sns_sketch& sk, const sns_matrix& A, const sns_solve_opts& o,
                  LstsqWs& w) {
-  if (sk.kind == SNS_SKETCH_GAUSSIAN) w.gauss = c.take<char>(gauss_workspace_bytes(A, (uint32_t)sk.d));
-  else carve_sketch(c, sk, A, true, o.accum_fp64 != 0, w.sw);
+  if (sk.kind == SNS_SKETCH_GAUSSIAN) {
+    w.gauss = c.take<char>(gauss_workspace_bytes(A, (uint32_t)sk.d));
+  } else if (A.layout == SNS_CSR) {
+    w.csr_bytes = csr_workspace_bytes(A, (uint32_t)sk.d, o.accum_fp64 != 0);
+    w.csr = c.take<char>(w.csr_bytes);
+  } else {
+    carve_sketch(c, sk, A, true, o.accum_fp64 != 0, w.sw);
+  }
   w.SA = c.take<char>((size_t)sk.d * A.n * elem(A));
   w.Sb = c.take<char>((size_t)sk.d * elem(A));
   carve_qr(c, sk.d, A.n, w.q);
@@ -139,6 +151,10 @@ sns_status sns_sketch_workspace_size(const sns_sketch* sk, const sns_matrix* A, 
     *bytes = gauss_workspace_bytes(*A, (uint32_t)sk->d);
     return SNS_OK;
   }
+  if (A->layout == SNS_CSR) {  // enough for either accumulator width
+    *bytes = csr_workspace_bytes(*A, (uint32_t)sk->d, true);
+    return SNS_OK;
+  }
   Carve c(nullptr, 0);
   SketchWs w;
   carve_sketch(c, *sk, *A, true, true, w);
@@ -160,6 +176,8 @@ sns_status sns_sketch_apply(const sns_sketch* sk, const sns_matrix* A, const voi
     if (ws_bytes < gauss_workspace_bytes(*A, (uint32_t)sk->d)) return SNS_ERR_OUT_OF_MEMORY;
     return launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, SA, Sb, workspace, st);
   }
+  if (A->layout == SNS_CSR)
+    return launch_csr_sketch(*A, (uint32_t)sk->d, sk->seed, b, SA, Sb, acc64, workspace, ws_bytes, st);
   Carve c(workspace, ws_bytes);
   SketchWs w;
   carve_sketch(c, *sk, *A, b != nullptr, acc64, w);
@@ -217,6 +235,7 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   if (o.refine && (o.max_iters < 0 || !(o.rtol >= 0.0))) return SNS_ERR_INVALID_ARG;
   if (A->n > 4096 || sk->d > kMaxQrD) return SNS_ERR_SHAPE;
   if (o.refine && A->n > 2048) return SNS_ERR_SHAPE;
+  if (o.refine && A->layout == SNS_CSR) return SNS_ERR_DTYPE;  // refinement streams dense rows
   if (o.refine && (((uintptr_t)A->values % 16) != 0 || (A->ld * elem(*A)) % 16 != 0))
     return SNS_ERR_SHAPE;
   Carve c(workspace, ws_bytes);
@@ -226,6 +245,9 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   hipStream_t st = (hipStream_t)stream;
   if (sk->kind == SNS_SKETCH_GAUSSIAN)
     s = launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, w.gauss, st);
+  else if (A->layout == SNS_CSR)
+    s = launch_csr_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, o.accum_fp64 != 0, w.csr,
+                          w.csr_bytes, st);
   else
     s = run_sketch(*sk, *A, b, w.SA, w.Sb, w.sw, st);
   if (s != SNS_OK) return s;

@@ -1,5 +1,6 @@
 // Stable counting sort of rows by CountSketch bucket (deterministic, integer
-// only).  Rows are cut into wave-blocks of `rw` consecutive rows; each wave
+// only).  The keys are the rows 0..m-1, or the m entries of an ascending row
+// list.  Keys are cut into wave-blocks of `rw` consecutive keys; each wave
 // histograms its block in LDS, a two-level exclusive scan in bucket-major
 // order turns the per-block counts into start offsets, and each wave then
 // places its rows in ascending order, ranking equal buckets within a batch of
@@ -23,8 +24,10 @@ __global__ void k_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uin
   }
 }
 
-// counts[wb * d + k] = number of rows of wave-block wb in bucket k.
+// counts[wb * d + k] = number of keys of wave-block wb in bucket k.  Key t is
+// row t, or row rows[t] when a row list is given.
 __global__ void k_sort_count(uint64_t seed, uint32_t d, int64_t m, int64_t rw, int64_t nwb,
+                             const uint32_t* __restrict__ rows, const uint32_t* __restrict__ mdev,
                              uint32_t* __restrict__ counts) {
   extern __shared__ uint32_t lds[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -32,13 +35,18 @@ __global__ void k_sort_count(uint64_t seed, uint32_t d, int64_t m, int64_t rw, i
   uint32_t* hist = lds + (size_t)wv * d;
   for (uint32_t k = lane; k < d; k += 64) hist[k] = 0u;
   __syncthreads();
+  if (mdev) m = *mdev;  // key count known only on the device
   if (wb < nwb) {
     const int64_t r0 = wb * rw, r1 = min(m, r0 + rw);  // r0 is even
-    for (int64_t j = (r0 >> 1) + lane; 2 * j < r1; j += 64) {
-      Hash e, o;
-      cs_hash_pair(seed, d, (uint64_t)j, e, o);
-      atomicAdd(&hist[e.h], 1u);
-      if (2 * j + 1 < r1) atomicAdd(&hist[o.h], 1u);
+    if (rows) {
+      for (int64_t t = r0 + lane; t < r1; t += 64) atomicAdd(&hist[cs_hash(seed, d, rows[t]).h], 1u);
+    } else {
+      for (int64_t j = (r0 >> 1) + lane; 2 * j < r1; j += 64) {
+        Hash e, o;
+        cs_hash_pair(seed, d, (uint64_t)j, e, o);
+        atomicAdd(&hist[e.h], 1u);
+        if (2 * j + 1 < r1) atomicAdd(&hist[o.h], 1u);
+      }
     }
   }
   __syncthreads();
@@ -105,25 +113,32 @@ __global__ void k_scan_buckets(uint32_t d, int64_t nseg, uint32_t* __restrict__ 
 
 template <typename BT>
 __global__ void k_sort_scatter(uint64_t seed, uint32_t d, int64_t m, int64_t rw, int64_t nwb,
-                               int64_t seg, const uint32_t* __restrict__ counts,
+                               int64_t seg, const uint32_t* __restrict__ rows,
+                               const uint32_t* __restrict__ mdev,
+                               const uint32_t* __restrict__ counts,
                                const uint32_t* __restrict__ segtot,
                                const uint32_t* __restrict__ bucket_ptr, const BT* __restrict__ b,
                                uint32_t* __restrict__ perm, BT* __restrict__ bperm) {
   extern __shared__ uint32_t lds[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t wb = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
-  uint32_t* next = lds + (size_t)wv * d;
-  if (wb < nwb) {
+  uint32_t* next = lds + (size_t)wv * d;  // this wave's own cursor per bucket
+  if (wb >= nwb) return;
+  if (mdev) m = *mdev;
+  const int64_t r0 = wb * rw, r1 = min(m, r0 + rw);
+  if (r0 >= r1) return;  // wave-block past the device-side key count
+  {
     const int64_t s = wb / seg;
     for (uint32_t k = lane; k < d; k += 64)
       next[k] = bucket_ptr[k] + segtot[s * d + k] + counts[wb * d + k];
   }
-  __syncthreads();
-  if (wb >= nwb) return;
-  const int64_t r0 = wb * rw, r1 = min(m, r0 + rw);
+  __builtin_amdgcn_wave_barrier();
+  uint32_t nrow = rows && r0 + lane < r1 ? rows[r0 + lane] : 0u;
   for (int64_t r = r0; r < r1; r += 64) {
-    const int64_t i = r + lane;
-    const bool valid = i < r1;
+    const int64_t tk = r + lane;
+    const bool valid = tk < r1;
+    const int64_t i = rows ? (int64_t)nrow : tk;
+    if (rows) nrow = tk + 64 < r1 ? rows[tk + 64] : 0u;  // next batch in flight
     const Hash hs = cs_hash(seed, d, (uint64_t)i);
     const uint32_t h = valid ? hs.h : 0xFFFFFFFFu;
     // rank among the earlier lanes of this batch with the same bucket
@@ -155,7 +170,11 @@ SortPlan make_sort_plan(int64_t m, uint32_t d) {
   SortPlan p;
   p.m = m;
   p.d = d;
+  // at most ~4096 wave-blocks, at least 512 keys each, and at least d / 2
+  // keys each so the d x nwb count matrix stays within ~2 entries per key
   int64_t rw = (m + 4095) / 4096;
+  const int64_t rd = (int64_t)d / 2;
+  rw = rw < rd ? rd : rw;
   rw = (rw + 63) / 64 * 64;
   p.rw = rw < 512 ? 512 : rw;
   p.nwb = (m + p.rw - 1) / p.rw;
@@ -175,24 +194,25 @@ void carve_sort(Carve& c, const SortPlan& p, size_t b_elem_bytes, SortBufs& s) {
 }
 
 sns_status launch_bucket_sort(const SortPlan& p, uint64_t seed, const void* b, sns_dtype bt,
-                              const SortBufs& s, hipStream_t st) {
+                              const SortBufs& s, hipStream_t st, const uint32_t* rows,
+                              const uint32_t* mdev) {
   const int nthr = p.waves * 64;
   const unsigned nblk = (unsigned)((p.nwb + p.waves - 1) / p.waves);
   const size_t lds = (size_t)p.waves * p.d * sizeof(uint32_t);
   SNS_LAUNCH("sort_count", k_sort_count, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m, p.rw, p.nwb,
-                     s.counts);
+             rows, mdev, s.counts);
   SNS_LAUNCH("scan_segments", k_scan_segments, dim3((p.d + 63) / 64, (unsigned)p.nseg), dim3(64), 0, st,
                      p.d, p.nwb, p.seg, s.counts, s.segtot);
   SNS_LAUNCH("scan_buckets", k_scan_buckets, dim3(1), dim3(1024), 0, st, p.d, p.nseg, s.segtot,
                      s.bucket_ptr);
   if (bt == SNS_F64 || !b) {
     SNS_LAUNCH("sort_scatter", k_sort_scatter<double>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
-                       p.rw, p.nwb, p.seg, s.counts, s.segtot, s.bucket_ptr,
+                       p.rw, p.nwb, p.seg, rows, mdev, s.counts, s.segtot, s.bucket_ptr,
                        static_cast<const double*>(b), s.perm,
                        b ? static_cast<double*>(s.bperm) : nullptr);
   } else {
     SNS_LAUNCH("sort_scatter", k_sort_scatter<float>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
-                       p.rw, p.nwb, p.seg, s.counts, s.segtot, s.bucket_ptr,
+                       p.rw, p.nwb, p.seg, rows, mdev, s.counts, s.segtot, s.bucket_ptr,
                        static_cast<const float*>(b), s.perm, static_cast<float*>(s.bperm));
   }
   SNS_HIP_TRY(hipGetLastError());

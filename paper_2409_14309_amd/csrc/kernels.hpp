@@ -60,8 +60,19 @@ struct SortBufs {
   uint32_t* segtot;
 };
 void carve_sort(Carve& c, const SortPlan& p, size_t b_elem_bytes, SortBufs& s);
+// rows (optional, ascending): sort rows[0..m) instead of 0..m-1; b is then
+// indexed by the row id.  mdev (optional): device-side key count <= p.m.
 sns_status launch_bucket_sort(const SortPlan& p, uint64_t seed, const void* b, sns_dtype bt,
-                              const SortBufs& s, hipStream_t st);
+                              const SortBufs& s, hipStream_t st, const uint32_t* rows = nullptr,
+                              const uint32_t* mdev = nullptr);
+
+// ------------------------------------------------------------------ CSR ----
+// CountSketch of a CSR matrix: SA (d x n, A's dtype) and, when b is given,
+// Sb (d).  Deterministic; see csr.hip.
+size_t csr_workspace_bytes(const sns_matrix& A, uint32_t d, bool acc64);
+sns_status launch_csr_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
+                             void* SA, void* Sb, bool acc64, void* ws, size_t ws_bytes,
+                             hipStream_t st);
 sns_status launch_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uint32_t* h,
                        int8_t* s, hipStream_t st);
 

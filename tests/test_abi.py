@@ -49,6 +49,15 @@ def test_host_side_argument_checks():
         (sns.Matrix(1000, 10, 1, 0, fake, 10, None, None, 0), sns.Sketch(1, 64, 1), 3),  # gaussian f64
         (sns.Matrix(1000, 10, 0, 0, fake, 10, None, None, 0), sns.Sketch(5, 64, 1), 1),  # bad kind
     ]
+    csr = dict(row_ptr=fake, col_idx=fake)
+    cases += [
+        (sns.Matrix(1000, 10, 0, 1, fake, 0, None, csr["col_idx"], 5), sk, 1),             # no row_ptr
+        (sns.Matrix(10000, 4097, 0, 1, fake, 0, csr["row_ptr"], csr["col_idx"], 5),
+         sns.Sketch(0, 5000, 1), 2),                                                      # CSR too wide
+        (sns.Matrix(1000, 10, 0, 1, fake, 0, csr["row_ptr"], csr["col_idx"], 5),
+         sns.Sketch(1, 64, 1), 3),                                                        # gaussian CSR
+        (sns.Matrix(1000, 10, 0, 1, fake, 0, csr["row_ptr"], csr["col_idx"], -1), sk, 2),  # nnz < 0
+    ]
     for A, s, want in cases:
         assert lib.sns_sketch_workspace_size(C.byref(s), C.byref(A), C.byref(nb)) == want
         assert lib.sns_sketch_apply(C.byref(s), C.byref(A), None, C.c_void_p(fake), None, None,
@@ -64,6 +73,11 @@ def test_host_side_argument_checks():
     o = sns.opts(refine=1, max_iters=-1)
     assert lib.sns_lstsq(C.byref(sk), C.byref(A), C.c_void_p(fake), C.c_void_p(fake), C.byref(o),
                          C.c_void_p(fake), 1 << 30, None, None) == 1
+    Ac = sns.Matrix(1000, 10, 0, 1, fake, 0, csr["row_ptr"], csr["col_idx"], 50)
+    assert lib.sns_sketch_workspace_size(C.byref(sk), C.byref(Ac), C.byref(nb)) == 0 and nb.value > 0
+    o = sns.opts(refine=1, max_iters=5)
+    assert lib.sns_lstsq(C.byref(sk), C.byref(Ac), C.c_void_p(fake), C.c_void_p(fake), C.byref(o),
+                         C.c_void_p(fake), 1 << 30, None, None) == 3                  # CSR refine
     assert lib.sns_qr_solve(10, 20, 0, C.c_void_p(fake), 20, C.c_void_p(fake), C.c_void_p(fake),
                             None, None, C.c_void_p(fake), 1 << 30, None) == 2
     assert lib.sns_hash(1, 0, 0, 10, C.c_void_p(fake), None, None) == 2
