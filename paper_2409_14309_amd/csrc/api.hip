@@ -46,7 +46,7 @@ sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A) {
 
 size_t elem(const sns_matrix& A) { return A.dtype == SNS_F64 ? 8 : 4; }
 
-// Workspace of the sketch step (sort + partials).
+// Workspace of the dense CountSketch step (sort + partials).
 struct SketchWs {
   SortPlan sp;
   GatherPlan gp;
@@ -63,11 +63,39 @@ void carve_sketch(Carve& c, const sns_sketch& sk, const sns_matrix& A, bool with
   w.part = pb ? (void*)c.take<char>(pb) : nullptr;
 }
 
-sns_status run_sketch(const sns_sketch& sk, const sns_matrix& A, const void* b, void* SA, void* Sb,
-                      const SketchWs& w, hipStream_t st) {
-  sns_status s = launch_bucket_sort(w.sp, sk.seed, b, A.dtype, w.sb, st);
+// The launch sequences of one call, built into one argument table.
+struct Jobs {
+  SortJob sort;
+  std::vector<GatherLaunch> gather;
+  QrJob qr;
+  LsqrJob lsqr;
+};
+
+void add_sketch_jobs(ArgTable& t, Jobs& J, const sns_sketch& sk, const sns_matrix& A,
+                     const void* b, void* SA, void* Sb, const SketchWs& w) {
+  const std::vector<SortArgs> sa{sort_args(w.sp, sk.seed, b, w.sb)};
+  J.sort = build_sort_job(t, sa, A.dtype == SNS_F64);
+  GatherProb g;
+  g.plan = w.gp;
+  g.args = gather_args(w.gp, A, (uint32_t)sk.d, w.sb, b != nullptr, SA, Sb, w.part);
+  g.dtype = A.dtype;
+  J.gather = build_gather_job(t, std::vector<GatherProb>{g});
+}
+
+sns_status run_sketch_jobs(const Jobs& J, hipStream_t st) {
+  sns_status s = launch_sort_job(J.sort, st);
   if (s != SNS_OK) return s;
-  return launch_cs_gather(w.gp, A, (uint32_t)sk.d, w.sb, b != nullptr, SA, Sb, w.part, st);
+  return launch_gather_job(J.gather, st);
+}
+
+// Argument-table bytes of a builder: a dry run against a table without a
+// device location (only sizes matter, so null pointers are fine).
+template <typename F>
+size_t table_bytes(F&& build) {
+  ArgTable t(nullptr);
+  Jobs J;
+  build(t, J);
+  return t.bytes();
 }
 
 struct LstsqWs {
@@ -81,10 +109,11 @@ struct LstsqWs {
   LsqrPlan lp;
   LsqrBufs l{};
   sns_info* info = nullptr;
+  char* args = nullptr;
 };
 
-void carve_lstsq(Carve& c, const sns_sketch& sk, const sns_matrix& A, const sns_solve_opts& o,
-                 LstsqWs& w) {
+void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
+                      const sns_solve_opts& o, LstsqWs& w) {
   if (sk.kind == SNS_SKETCH_GAUSSIAN) {
     w.gauss = c.take<char>(gauss_workspace_bytes(A, (uint32_t)sk.d));
   } else if (A.layout == SNS_CSR) {
@@ -101,6 +130,32 @@ void carve_lstsq(Carve& c, const sns_sketch& sk, const sns_matrix& A, const sns_
     carve_lsqr(c, A, w.lp, w.l);
   }
   w.info = c.take<sns_info>(1);
+}
+
+void build_lstsq_jobs(ArgTable& t, Jobs& J, const sns_sketch& sk, const sns_matrix& A,
+                      const void* b, double* x, const sns_solve_opts& o, const LstsqWs& w) {
+  if (sk.kind == SNS_SKETCH_COUNT && A.layout == SNS_DENSE_ROWMAJOR)
+    add_sketch_jobs(t, J, sk, A, b, w.SA, w.Sb, w.sw);
+  const std::vector<QrArgs> qa{
+      qr_args(sk.d, A.n, w.SA, A.n, w.Sb, w.q, w.q.xw, nullptr, w.info)};
+  J.qr = build_qr_job(t, qa, A.dtype == SNS_F64);
+  if (o.refine) {
+    LsqrProb lp;
+    lp.plan = w.lp;
+    lp.args = lsqr_args(A, b, w.lp, w.l, w.q, (int)sk.d, o.max_iters, o.rtol, x, w.info);
+    J.lsqr = build_lsqr_job(t, std::vector<LsqrProb>{lp}, A.dtype == SNS_F64);
+  }
+}
+
+// Full workspace layout of sns_lstsq: buffers, then the argument table.
+void carve_lstsq(Carve& c, const sns_sketch& sk, const sns_matrix& A, const sns_solve_opts& o,
+                 LstsqWs& w) {
+  carve_lstsq_bufs(c, sk, A, o, w);
+  const LstsqWs wz = w;
+  const size_t tb = table_bytes([&](ArgTable& t, Jobs& J) {
+    build_lstsq_jobs(t, J, sk, A, nullptr, nullptr, o, wz);
+  });
+  w.args = c.take<char>(tb);
 }
 
 sns_solve_opts default_opts() {
@@ -158,6 +213,12 @@ sns_status sns_sketch_workspace_size(const sns_sketch* sk, const sns_matrix* A, 
   Carve c(nullptr, 0);
   SketchWs w;
   carve_sketch(c, *sk, *A, true, true, w);
+  const sns_sketch skv = *sk;
+  const sns_matrix Av = *A;
+  const size_t tb = table_bytes([&](ArgTable& t, Jobs& J) {
+    add_sketch_jobs(t, J, skv, Av, (const void*)1, nullptr, nullptr, w);
+  });
+  c.take<char>(tb);
   *bytes = c.off;
   return SNS_OK;
 }
@@ -181,14 +242,34 @@ sns_status sns_sketch_apply(const sns_sketch* sk, const sns_matrix* A, const voi
   Carve c(workspace, ws_bytes);
   SketchWs w;
   carve_sketch(c, *sk, *A, b != nullptr, acc64, w);
+  const sns_sketch skv = *sk;
+  const sns_matrix Av = *A;
+  const size_t tb = table_bytes([&](ArgTable& t, Jobs& J) {
+    add_sketch_jobs(t, J, skv, Av, b, nullptr, nullptr, w);
+  });
+  char* args = c.take<char>(tb);
   if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
-  return run_sketch(*sk, *A, b, SA, Sb, w, st);
+  ArgTable t(args);
+  Jobs J;
+  add_sketch_jobs(t, J, skv, Av, b, SA, Sb, w);
+  sns_status s2 = t.upload(st);
+  if (s2 != SNS_OK) return s2;
+  return run_sketch_jobs(J, st);
 }
 
 sns_status sns_qr_solve_workspace_size(int64_t d, int64_t n, size_t* bytes) {
   if (!bytes) return SNS_ERR_INVALID_ARG;
   if (n < 1 || d < n || d > kMaxQrD || n > 4096) return SNS_ERR_SHAPE;
-  *bytes = qr_workspace_bytes(d, n) + align_up(sizeof(sns_info));
+  Carve c(nullptr, 0);
+  QrBufs q;
+  carve_qr(c, d, n, q);
+  c.take<sns_info>(1);
+  ArgTable t(nullptr);
+  build_qr_job(t, std::vector<QrArgs>{qr_args(d, n, nullptr, n, nullptr, q, nullptr, nullptr,
+                                               nullptr)},
+               false);
+  c.take<char>(t.bytes());
+  *bytes = c.off;
   return SNS_OK;
 }
 
@@ -202,10 +283,17 @@ sns_status sns_qr_solve(int64_t d, int64_t n, sns_dtype dtype, const void* SA, i
   QrBufs q;
   carve_qr(c, d, n, q);
   sns_info* idev = c.take<sns_info>(1);
+  const std::vector<QrArgs> qa{qr_args(d, n, SA, ld_sa, Sb, q, x0, R, idev)};
+  ArgTable t0(nullptr);
+  build_qr_job(t0, qa, dtype == SNS_F64);
+  char* args = c.take<char>(t0.bytes());
   if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
   hipStream_t st = (hipStream_t)stream;
-  sns_status s = launch_qr_solve(d, n, dtype, SA, ld_sa, Sb, q, x0, R, idev, st);
+  ArgTable t(args);
+  const QrJob job = build_qr_job(t, qa, dtype == SNS_F64);
+  sns_status s = t.upload(st);
   if (s != SNS_OK) return s;
+  if ((s = launch_qr_job(job, st)) != SNS_OK) return s;
   if (info) SNS_HIP_TRY(hipMemcpyAsync(info, idev, sizeof(sns_info), hipMemcpyDeviceToHost, st));
   return SNS_OK;
 }
@@ -243,19 +331,21 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   carve_lstsq(c, *sk, *A, o, w);
   if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
   hipStream_t st = (hipStream_t)stream;
+  ArgTable t(w.args);
+  Jobs J;
+  build_lstsq_jobs(t, J, *sk, *A, b, x, o, w);
+  if ((s = t.upload(st)) != SNS_OK) return s;
   if (sk->kind == SNS_SKETCH_GAUSSIAN)
     s = launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, w.gauss, st);
   else if (A->layout == SNS_CSR)
     s = launch_csr_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, o.accum_fp64 != 0, w.csr,
                           w.csr_bytes, st);
   else
-    s = run_sketch(*sk, *A, b, w.SA, w.Sb, w.sw, st);
+    s = run_sketch_jobs(J, st);
   if (s != SNS_OK) return s;
-  s = launch_qr_solve(sk->d, A->n, A->dtype, w.SA, A->n, w.Sb, w.q, w.q.xw, nullptr, w.info, st);
-  if (s != SNS_OK) return s;
+  if ((s = launch_qr_job(J.qr, st)) != SNS_OK) return s;
   if (o.refine) {
-    s = launch_sap_refine(*A, b, w.lp, w.l, w.q, (int)sk->d, o.max_iters, o.rtol, x, w.info, st);
-    if (s != SNS_OK) return s;
+    if ((s = run_lsqr_single(J.lsqr, o.max_iters, true, st)) != SNS_OK) return s;
   } else {
     SNS_HIP_TRY(hipMemcpyAsync(x, w.q.xw, sizeof(double) * A->n, hipMemcpyDeviceToDevice, st));
   }

@@ -25,69 +25,84 @@ __global__ void k_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uin
 }
 
 // counts[wb * d + k] = number of keys of wave-block wb in bucket k.  Key t is
-// row t, or row rows[t] when a row list is given.
-__global__ void k_sort_count(uint64_t seed, uint32_t d, int64_t m, int64_t rw, int64_t nwb,
-                             const uint32_t* __restrict__ rows, const uint32_t* __restrict__ mdev,
-                             uint32_t* __restrict__ counts) {
-  extern __shared__ uint32_t lds[];
+// row t, or row rows[t] when a row list is given.  A work item is `waves`
+// consecutive wave-blocks of one problem.
+__device__ __forceinline__ void sort_count_item(const SortArgs& a, uint32_t loc, int waves,
+                                                uint32_t* lds) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t wb = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  const uint32_t d = a.d;
+  const int64_t wb = (int64_t)loc * waves + wv;
   uint32_t* hist = lds + (size_t)wv * d;
   for (uint32_t k = lane; k < d; k += 64) hist[k] = 0u;
   __syncthreads();
-  if (mdev) m = *mdev;  // key count known only on the device
-  if (wb < nwb) {
-    const int64_t r0 = wb * rw, r1 = min(m, r0 + rw);  // r0 is even
-    if (rows) {
-      for (int64_t t = r0 + lane; t < r1; t += 64) atomicAdd(&hist[cs_hash(seed, d, rows[t]).h], 1u);
+  const int64_t m = a.mdev ? (int64_t)*a.mdev : a.m;  // key count known only on the device
+  if (wb < a.nwb) {
+    const int64_t r0 = wb * a.rw, r1 = min(m, r0 + a.rw);  // r0 is even
+    if (a.rows) {
+      for (int64_t t = r0 + lane; t < r1; t += 64)
+        atomicAdd(&hist[cs_hash(a.seed, d, a.rows[t]).h], 1u);
     } else {
       for (int64_t j = (r0 >> 1) + lane; 2 * j < r1; j += 64) {
         Hash e, o;
-        cs_hash_pair(seed, d, (uint64_t)j, e, o);
+        cs_hash_pair(a.seed, d, (uint64_t)j, e, o);
         atomicAdd(&hist[e.h], 1u);
         if (2 * j + 1 < r1) atomicAdd(&hist[o.h], 1u);
       }
     }
   }
   __syncthreads();
-  if (wb < nwb)
-    for (uint32_t k = lane; k < d; k += 64) counts[wb * d + k] = hist[k];
+  if (wb < a.nwb)
+    for (uint32_t k = lane; k < d; k += 64) a.counts[wb * d + k] = hist[k];
+}
+
+__global__ void k_sort_count(const SortArgs* __restrict__ P, Map mp, int waves) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  sort_count_item(P[pi], it - mp.off[pi], waves, lds);
 }
 
 // Within each segment of `seg` wave-blocks, replace counts by their exclusive
-// prefix (per bucket) and record the segment totals.
-__global__ void k_scan_segments(uint32_t d, int64_t nwb, int64_t seg, uint32_t* __restrict__ counts,
-                                uint32_t* __restrict__ segtot) {
-  const uint32_t k = blockIdx.x * 64 + threadIdx.x;
-  const int64_t s = blockIdx.y;
-  if (k >= d) return;
-  const int64_t w0 = s * seg, w1 = min(nwb, w0 + seg);
+// prefix (per bucket) and record the segment totals.  A work item is 64
+// buckets of one segment.
+__global__ void k_scan_segments(const SortArgs* __restrict__ P, Map mp) {
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  const SortArgs& a = P[pi];
+  const uint32_t loc = it - mp.off[pi];
+  const uint32_t kb = (a.d + 63) / 64;
+  const uint32_t k = (loc % kb) * 64 + threadIdx.x;
+  const int64_t s = loc / kb;
+  if (k >= a.d) return;
+  const int64_t w0 = s * a.seg, w1 = min(a.nwb, w0 + a.seg);
   uint32_t run = 0;
   for (int64_t wb = w0; wb < w1; ++wb) {
-    const uint32_t c = counts[wb * d + k];
-    counts[wb * d + k] = run;
+    const uint32_t c = a.counts[wb * a.d + k];
+    a.counts[wb * a.d + k] = run;
     run += c;
   }
-  segtot[s * d + k] = run;
+  a.segtot[s * a.d + k] = run;
 }
 
 // Exclusive scan across segments per bucket (in place in segtot), then across
-// buckets: bucket_ptr[k] = rows in buckets < k, bucket_ptr[d] = m.
-__global__ void k_scan_buckets(uint32_t d, int64_t nseg, uint32_t* __restrict__ segtot,
-                               uint32_t* __restrict__ bucket_ptr) {
-  __shared__ uint32_t wsum[16];
-  const int t = threadIdx.x, nt = blockDim.x;  // 1024 threads
+// buckets: bucket_ptr[k] = rows in buckets < k, bucket_ptr[d] = m.  One work
+// item (1024 threads) per problem.
+__device__ __forceinline__ void scan_buckets_item(const SortArgs& a, uint32_t* wsum) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const uint32_t d = a.d;
   const uint32_t per = (d + nt - 1) / nt;
   const uint32_t k0 = min(d, t * per), k1 = min(d, k0 + per);
   uint32_t local = 0;
   for (uint32_t k = k0; k < k1; ++k) {
     uint32_t run = 0;
-    for (int64_t s = 0; s < nseg; ++s) {
-      const uint32_t c = segtot[s * d + k];
-      segtot[s * d + k] = run;
+    for (int64_t s = 0; s < a.nseg; ++s) {
+      const uint32_t c = a.segtot[s * d + k];
+      a.segtot[s * d + k] = run;
       run += c;
     }
-    bucket_ptr[k] = run;  // bucket total for now
+    a.bucket_ptr[k] = run;  // bucket total for now
     local += run;
   }
   // exclusive scan of `local` over threads
@@ -104,42 +119,47 @@ __global__ void k_scan_buckets(uint32_t d, int64_t nseg, uint32_t* __restrict__ 
   for (int w = 0; w < wv; ++w) before += wsum[w];
   uint32_t run = before + incl - local;
   for (uint32_t k = k0; k < k1; ++k) {
-    const uint32_t c = bucket_ptr[k];
-    bucket_ptr[k] = run;
+    const uint32_t c = a.bucket_ptr[k];
+    a.bucket_ptr[k] = run;
     run += c;
   }
-  if (t == nt - 1) bucket_ptr[d] = run;
+  if (t == nt - 1) a.bucket_ptr[d] = run;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_buckets(const SortArgs* __restrict__ P, Map mp) {
+  __shared__ uint32_t wsum[16];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  scan_buckets_item(P[map_find(mp, it)], wsum);
 }
 
 template <typename BT>
-__global__ void k_sort_scatter(uint64_t seed, uint32_t d, int64_t m, int64_t rw, int64_t nwb,
-                               int64_t seg, const uint32_t* __restrict__ rows,
-                               const uint32_t* __restrict__ mdev,
-                               const uint32_t* __restrict__ counts,
-                               const uint32_t* __restrict__ segtot,
-                               const uint32_t* __restrict__ bucket_ptr, const BT* __restrict__ b,
-                               uint32_t* __restrict__ perm, BT* __restrict__ bperm) {
-  extern __shared__ uint32_t lds[];
+__device__ __forceinline__ void sort_scatter_item(const SortArgs& a, uint32_t loc, int waves,
+                                                  uint32_t* lds) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t wb = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  const uint32_t d = a.d;
+  const int64_t wb = (int64_t)loc * waves + wv;
   uint32_t* next = lds + (size_t)wv * d;  // this wave's own cursor per bucket
-  if (wb >= nwb) return;
-  if (mdev) m = *mdev;
-  const int64_t r0 = wb * rw, r1 = min(m, r0 + rw);
+  if (wb >= a.nwb) return;
+  const int64_t m = a.mdev ? (int64_t)*a.mdev : a.m;
+  const int64_t r0 = wb * a.rw, r1 = min(m, r0 + a.rw);
   if (r0 >= r1) return;  // wave-block past the device-side key count
   {
-    const int64_t s = wb / seg;
+    const int64_t s = wb / a.seg;
     for (uint32_t k = lane; k < d; k += 64)
-      next[k] = bucket_ptr[k] + segtot[s * d + k] + counts[wb * d + k];
+      next[k] = a.bucket_ptr[k] + a.segtot[s * d + k] + a.counts[wb * d + k];
   }
   __builtin_amdgcn_wave_barrier();
+  const uint32_t* rows = a.rows;
+  const BT* b = static_cast<const BT*>(a.b);
+  BT* bperm = static_cast<BT*>(a.bperm);
   uint32_t nrow = rows && r0 + lane < r1 ? rows[r0 + lane] : 0u;
   for (int64_t r = r0; r < r1; r += 64) {
     const int64_t tk = r + lane;
     const bool valid = tk < r1;
     const int64_t i = rows ? (int64_t)nrow : tk;
     if (rows) nrow = tk + 64 < r1 ? rows[tk + 64] : 0u;  // next batch in flight
-    const Hash hs = cs_hash(seed, d, (uint64_t)i);
+    const Hash hs = cs_hash(a.seed, d, (uint64_t)i);
     const uint32_t h = valid ? hs.h : 0xFFFFFFFFu;
     // rank among the earlier lanes of this batch with the same bucket
     uint32_t rank = 0;
@@ -154,7 +174,7 @@ __global__ void k_sort_scatter(uint64_t seed, uint32_t d, int64_t m, int64_t rw,
     }
     if (valid) {
       const uint32_t pos = next[h] + rank;
-      perm[pos] = (uint32_t)i | (hs.neg ? 0x80000000u : 0u);
+      a.perm[pos] = (uint32_t)i | (hs.neg ? 0x80000000u : 0u);
       if (bperm) {
         const BT v = b[i];
         bperm[pos] = hs.neg ? -v : v;
@@ -162,6 +182,20 @@ __global__ void k_sort_scatter(uint64_t seed, uint32_t d, int64_t m, int64_t rw,
       if (last) next[h] = pos + 1;
     }
   }
+}
+
+template <typename BT>
+__global__ void k_sort_scatter(const SortArgs* __restrict__ P, Map mp, int waves) {
+  extern __shared__ uint32_t lds[];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  sort_scatter_item<BT>(P[pi], it - mp.off[pi], waves, lds);
+}
+
+int sort_waves(uint32_t maxd) {
+  const int w = (int)(16384 / maxd);
+  return w < 1 ? 1 : (w > 4 ? 4 : w);
 }
 
 }  // namespace
@@ -178,8 +212,6 @@ SortPlan make_sort_plan(int64_t m, uint32_t d) {
   rw = (rw + 63) / 64 * 64;
   p.rw = rw < 512 ? 512 : rw;
   p.nwb = (m + p.rw - 1) / p.rw;
-  int w = (int)(16384 / d);
-  p.waves = w < 1 ? 1 : (w > 4 ? 4 : w);
   p.seg = 64;
   p.nseg = (p.nwb + p.seg - 1) / p.seg;
   return p;
@@ -193,28 +225,64 @@ void carve_sort(Carve& c, const SortPlan& p, size_t b_elem_bytes, SortBufs& s) {
   s.segtot = c.take<uint32_t>((size_t)p.d * p.nseg);
 }
 
-sns_status launch_bucket_sort(const SortPlan& p, uint64_t seed, const void* b, sns_dtype bt,
-                              const SortBufs& s, hipStream_t st, const uint32_t* rows,
-                              const uint32_t* mdev) {
-  const int nthr = p.waves * 64;
-  const unsigned nblk = (unsigned)((p.nwb + p.waves - 1) / p.waves);
-  const size_t lds = (size_t)p.waves * p.d * sizeof(uint32_t);
-  SNS_LAUNCH("sort_count", k_sort_count, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m, p.rw, p.nwb,
-             rows, mdev, s.counts);
-  SNS_LAUNCH("scan_segments", k_scan_segments, dim3((p.d + 63) / 64, (unsigned)p.nseg), dim3(64), 0, st,
-                     p.d, p.nwb, p.seg, s.counts, s.segtot);
-  SNS_LAUNCH("scan_buckets", k_scan_buckets, dim3(1), dim3(1024), 0, st, p.d, p.nseg, s.segtot,
-                     s.bucket_ptr);
-  if (bt == SNS_F64 || !b) {
-    SNS_LAUNCH("sort_scatter", k_sort_scatter<double>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
-                       p.rw, p.nwb, p.seg, rows, mdev, s.counts, s.segtot, s.bucket_ptr,
-                       static_cast<const double*>(b), s.perm,
-                       b ? static_cast<double*>(s.bperm) : nullptr);
-  } else {
-    SNS_LAUNCH("sort_scatter", k_sort_scatter<float>, dim3(nblk), dim3(nthr), lds, st, seed, p.d, p.m,
-                       p.rw, p.nwb, p.seg, rows, mdev, s.counts, s.segtot, s.bucket_ptr,
-                       static_cast<const float*>(b), s.perm, static_cast<float*>(s.bperm));
+SortArgs sort_args(const SortPlan& p, uint64_t seed, const void* b, const SortBufs& s,
+                   const uint32_t* rows, const uint32_t* mdev) {
+  SortArgs a;
+  a.seed = seed;
+  a.m = p.m;
+  a.rw = p.rw;
+  a.nwb = p.nwb;
+  a.seg = p.seg;
+  a.nseg = p.nseg;
+  a.d = p.d;
+  a.rows = rows;
+  a.mdev = mdev;
+  a.b = b;
+  a.perm = s.perm;
+  a.bperm = b ? s.bperm : nullptr;
+  a.bucket_ptr = s.bucket_ptr;
+  a.counts = s.counts;
+  a.segtot = s.segtot;
+  return a;
+}
+
+SortJob build_sort_job(ArgTable& t, const std::vector<SortArgs>& a, bool f64) {
+  SortJob j;
+  j.count = (int)a.size();
+  j.f64 = f64;
+  if (a.empty()) return j;
+  for (const SortArgs& x : a) j.maxd = x.d > j.maxd ? x.d : j.maxd;
+  const int waves = sort_waves(j.maxd);
+  std::vector<uint32_t> cnt, seg, one;
+  for (const SortArgs& x : a) {
+    cnt.push_back((uint32_t)((x.nwb + waves - 1) / waves));
+    seg.push_back((uint32_t)(((x.d + 63) / 64) * x.nseg));
+    one.push_back(1u);
   }
+  j.args = t.add(a.data(), a.size());
+  j.mcount = t.map(cnt, &j.ncount);
+  j.mseg = t.map(seg, &j.nseg);
+  j.mscan = t.map(one, &j.nscan);
+  return j;
+}
+
+sns_status launch_sort_job(const SortJob& j, hipStream_t st) {
+  if (j.count == 0) return SNS_OK;
+  const int waves = sort_waves(j.maxd);
+  const int nthr = waves * 64;
+  const size_t lds = (size_t)waves * j.maxd * sizeof(uint32_t);
+  SNS_LAUNCH("sort_count", k_sort_count, dim3(grid_for(j.ncount)), dim3(nthr), lds, st, j.args,
+             j.mcount, waves);
+  SNS_LAUNCH("scan_segments", k_scan_segments, dim3(grid_for(j.nseg)), dim3(64), 0, st, j.args,
+             j.mseg);
+  SNS_LAUNCH("scan_buckets", k_scan_buckets, dim3(grid_for(j.nscan)), dim3(1024), 0, st, j.args,
+             j.mscan);
+  if (j.f64)
+    SNS_LAUNCH("sort_scatter", k_sort_scatter<double>, dim3(grid_for(j.ncount)), dim3(nthr), lds,
+               st, j.args, j.mcount, waves);
+  else
+    SNS_LAUNCH("sort_scatter", k_sort_scatter<float>, dim3(grid_for(j.ncount)), dim3(nthr), lds,
+               st, j.args, j.mcount, waves);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }

@@ -42,25 +42,27 @@ __device__ __forceinline__ void load_row(const T* __restrict__ p, int col, int n
   }
 }
 
+// One work item: bucket k, segment sg, column tile ct of one problem.
 template <typename T, typename Acc, int VEC, int LPR, int WAVES, int U>
-__global__ __launch_bounds__(WAVES * 64) void k_cs_gather(
-    const T* __restrict__ A, int64_t ld, int n, const uint32_t* __restrict__ perm,
-    const T* __restrict__ bperm, const uint32_t* __restrict__ bucket_ptr, uint32_t d, int nseg,
-    T* __restrict__ SA, T* __restrict__ Sb, Acc* __restrict__ partA, Acc* __restrict__ partB) {
+__device__ __forceinline__ void cs_gather_item(const GatherArgs& a, uint32_t loc, Acc* red,
+                                               Acc* redb) {
   constexpr int RPW = 64 / LPR;
   constexpr int CT = LPR * VEC;
   constexpr int NS = WAVES * RPW;
-  __shared__ Acc red[NS * CT];
-  __shared__ Acc redb[NS];
-
-  const uint32_t k = blockIdx.x / nseg;
-  const int sg = blockIdx.x % nseg;
-  const int64_t p0 = bucket_ptr[k], p1 = bucket_ptr[k + 1], len = p1 - p0;
+  const T* __restrict__ A = static_cast<const T*>(a.A);
+  const T* __restrict__ bperm = static_cast<const T*>(a.bperm);
+  const int64_t ld = a.ld;
+  const int n = a.n, nseg = a.nseg;
+  const uint32_t d = a.d;
+  const uint32_t bx = loc % (d * (uint32_t)nseg), ct = loc / (d * (uint32_t)nseg);
+  const uint32_t k = bx / nseg;
+  const int sg = bx % nseg;
+  const int64_t p0 = a.bucket_ptr[k], p1 = a.bucket_ptr[k + 1], len = p1 - p0;
   const int64_t s0 = p0 + len * sg / nseg, s1 = p0 + len * (sg + 1) / nseg;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int slot = wv * RPW + lane / LPR, lr = lane % LPR;
-  const int col = blockIdx.y * CT + lr * VEC;
-  const bool do_b = (bperm != nullptr) && blockIdx.y == 0;
+  const int col = ct * CT + lr * VEC;
+  const bool do_b = (bperm != nullptr) && ct == 0;
 
   Acc acc[VEC];
 #pragma unroll
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_cs_gather(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t pu = p + (int64_t)u * NS;
-      e[u] = pu < s1 ? perm[pu] : 0xFFFFFFFFu;
+      e[u] = pu < s1 ? a.perm[pu] : 0xFFFFFFFFu;
       bv[u] = (do_b && pu < s1) ? bperm[pu] : T(0);
     }
 #pragma unroll
@@ -106,36 +108,56 @@ __global__ __launch_bounds__(WAVES * 64) void k_cs_gather(
   for (int t = threadIdx.x; t < CT; t += blockDim.x) {
     Acc s = Acc(0);
     for (int q = 0; q < NS; ++q) s += red[q * CT + t];
-    const int c = blockIdx.y * CT + t;
+    const int c = ct * CT + t;
     if (c < n) {
-      if (nseg == 1) SA[(size_t)k * n + c] = (T)s;
-      else partA[((size_t)sg * d + k) * n + c] = s;
+      if (nseg == 1) static_cast<T*>(a.SA)[(size_t)k * n + c] = (T)s;
+      else static_cast<Acc*>(a.partA)[((size_t)sg * d + k) * n + c] = s;
     }
   }
   if (do_b && threadIdx.x == 0) {
     Acc s = Acc(0);
     for (int q = 0; q < NS; ++q) s += redb[q];
-    if (nseg == 1) Sb[k] = (T)s;
-    else partB[(size_t)sg * d + k] = s;
+    if (nseg == 1) static_cast<T*>(a.Sb)[k] = (T)s;
+    else static_cast<Acc*>(a.partB)[(size_t)sg * d + k] = s;
   }
 }
 
-// SA = sum over segments (ascending) of the partial sketches.
+template <typename T, typename Acc, int VEC, int LPR, int WAVES, int U>
+__global__ __launch_bounds__(WAVES * 64) void k_cs_gather(const GatherArgs* __restrict__ P,
+                                                          Map mp) {
+  constexpr int CT = LPR * VEC;
+  constexpr int NS = WAVES * (64 / LPR);
+  __shared__ Acc red[NS * CT];
+  __shared__ Acc redb[NS];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  cs_gather_item<T, Acc, VEC, LPR, WAVES, U>(P[pi], it - mp.off[pi], red, redb);
+}
+
+// SA = sum over segments (ascending) of the partial sketches.  A work item is
+// 256 consecutive outputs of one problem.
 template <typename T, typename Acc>
-__global__ void k_seg_reduce(int64_t dn, int64_t d, int nseg, const Acc* __restrict__ partA,
-                             const Acc* __restrict__ partB, T* __restrict__ SA,
-                             T* __restrict__ Sb) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < dn + d;
-       t += (int64_t)gridDim.x * blockDim.x) {
+__global__ void k_seg_reduce(const GatherArgs* __restrict__ P, Map mp) {
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  const GatherArgs& a = P[pi];
+  const uint32_t loc = it - mp.off[pi];
+  const int64_t d = a.d, dn = d * a.n;
+  const Acc* partA = static_cast<const Acc*>(a.partA);
+  const Acc* partB = static_cast<const Acc*>(a.partB);
+  for (int64_t t = (int64_t)loc * blockDim.x + threadIdx.x; t < dn + d;
+       t += (int64_t)a.red_blocks * blockDim.x) {
     if (t < dn) {
       Acc s = Acc(0);
-      for (int g = 0; g < nseg; ++g) s += partA[(size_t)g * dn + t];
-      SA[t] = (T)s;
-    } else if (partB) {
+      for (int g = 0; g < a.nseg; ++g) s += partA[(size_t)g * dn + t];
+      static_cast<T*>(a.SA)[t] = (T)s;
+    } else if (a.bperm) {
       const int64_t k = t - dn;
       Acc s = Acc(0);
-      for (int g = 0; g < nseg; ++g) s += partB[(size_t)g * d + k];
-      Sb[k] = (T)s;
+      for (int g = 0; g < a.nseg; ++g) s += partB[(size_t)g * d + k];
+      static_cast<T*>(a.Sb)[k] = (T)s;
     }
   }
 }
@@ -144,34 +166,22 @@ constexpr int kWaves = 4;
 constexpr int kUnroll = 4;
 
 template <typename T, typename Acc, int VEC, int LPR>
-void launch_one(const GatherPlan& g, const sns_matrix& A, uint32_t d, const SortBufs& s,
-                bool with_b, void* SA, void* Sb, void* part, hipStream_t st) {
-  const dim3 grid(d * g.nseg, g.coltiles);
-  Acc* pa = g.nseg > 1 ? static_cast<Acc*>(part) : nullptr;
-  Acc* pb = (g.nseg > 1 && with_b) ? pa + (size_t)g.nseg * d * A.n : nullptr;
-  SNS_LAUNCH("cs_gather", (k_cs_gather<T, Acc, VEC, LPR, kWaves, kUnroll>), grid, dim3(kWaves * 64), 0,
-                     st, static_cast<const T*>(A.values), A.ld, (int)A.n, s.perm,
-                     with_b ? static_cast<const T*>(s.bperm) : nullptr, s.bucket_ptr, d, g.nseg,
-                     static_cast<T*>(SA), static_cast<T*>(Sb), pa, pb);
-  if (g.nseg > 1) {
-    const int64_t dn = (int64_t)d * A.n;
-    int64_t blocks = (dn + d + 255) / 256;
-    if (blocks > 4096) blocks = 4096;
-    SNS_LAUNCH("seg_reduce", (k_seg_reduce<T, Acc>), dim3((unsigned)blocks), dim3(256), 0, st, dn,
-                       (int64_t)d, g.nseg, pa, pb, static_cast<T*>(SA),
-                       with_b ? static_cast<T*>(Sb) : nullptr);
-  }
+void launch_one(const GatherLaunch& g, hipStream_t st) {
+  SNS_LAUNCH("cs_gather", (k_cs_gather<T, Acc, VEC, LPR, kWaves, kUnroll>), dim3(grid_for(g.items)),
+             dim3(kWaves * 64), 0, st, g.args, g.map);
+  if (g.ritems)
+    SNS_LAUNCH("seg_reduce", (k_seg_reduce<T, Acc>), dim3(grid_for(g.ritems)), dim3(256), 0, st,
+               g.rargs, g.rmap);
 }
 
 template <typename T, typename Acc, int VEC>
-void dispatch_lpr(const GatherPlan& g, const sns_matrix& A, uint32_t d, const SortBufs& s,
-                  bool with_b, void* SA, void* Sb, void* part, hipStream_t st) {
-  switch (g.lpr) {
-    case 4: launch_one<T, Acc, VEC, 4>(g, A, d, s, with_b, SA, Sb, part, st); break;
-    case 8: launch_one<T, Acc, VEC, 8>(g, A, d, s, with_b, SA, Sb, part, st); break;
-    case 16: launch_one<T, Acc, VEC, 16>(g, A, d, s, with_b, SA, Sb, part, st); break;
-    case 32: launch_one<T, Acc, VEC, 32>(g, A, d, s, with_b, SA, Sb, part, st); break;
-    default: launch_one<T, Acc, VEC, 64>(g, A, d, s, with_b, SA, Sb, part, st); break;
+void dispatch_lpr(const GatherLaunch& g, hipStream_t st) {
+  switch (g.plan.lpr) {
+    case 4: launch_one<T, Acc, VEC, 4>(g, st); break;
+    case 8: launch_one<T, Acc, VEC, 8>(g, st); break;
+    case 16: launch_one<T, Acc, VEC, 16>(g, st); break;
+    case 32: launch_one<T, Acc, VEC, 32>(g, st); break;
+    default: launch_one<T, Acc, VEC, 64>(g, st); break;
   }
 }
 
@@ -206,18 +216,80 @@ size_t gather_partial_bytes(const GatherPlan& g, const sns_matrix& A, uint32_t d
   return (size_t)g.nseg * d * (A.n + 1) * (g.acc64 ? 8 : 4);
 }
 
-sns_status launch_cs_gather(const GatherPlan& g, const sns_matrix& A, uint32_t d,
-                            const SortBufs& s, bool with_b, void* SA, void* Sb, void* part,
-                            hipStream_t st) {
-  if (A.dtype == SNS_F64) {
-    if (g.vec == 2) dispatch_lpr<double, double, 2>(g, A, d, s, with_b, SA, Sb, part, st);
-    else dispatch_lpr<double, double, 1>(g, A, d, s, with_b, SA, Sb, part, st);
-  } else if (g.acc64) {
-    if (g.vec == 4) dispatch_lpr<float, double, 4>(g, A, d, s, with_b, SA, Sb, part, st);
-    else dispatch_lpr<float, double, 1>(g, A, d, s, with_b, SA, Sb, part, st);
-  } else {
-    if (g.vec == 4) dispatch_lpr<float, float, 4>(g, A, d, s, with_b, SA, Sb, part, st);
-    else dispatch_lpr<float, float, 1>(g, A, d, s, with_b, SA, Sb, part, st);
+GatherArgs gather_args(const GatherPlan& g, const sns_matrix& A, uint32_t d, const SortBufs& s,
+                       bool with_b, void* SA, void* Sb, void* part) {
+  GatherArgs a;
+  a.A = A.values;
+  a.ld = A.ld;
+  a.n = (int)A.n;
+  a.nseg = g.nseg;
+  a.coltiles = g.coltiles;
+  a.d = d;
+  a.perm = s.perm;
+  a.bperm = with_b ? s.bperm : nullptr;
+  a.bucket_ptr = s.bucket_ptr;
+  a.SA = SA;
+  a.Sb = with_b ? Sb : nullptr;
+  const size_t ab = g.acc64 ? 8 : 4;
+  a.partA = g.nseg > 1 ? part : nullptr;
+  a.partB = (g.nseg > 1 && with_b) ? static_cast<char*>(part) + (size_t)g.nseg * d * A.n * ab
+                                   : nullptr;
+  const int64_t dn = (int64_t)d * A.n;
+  int64_t blocks = (dn + d + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  a.red_blocks = (int)blocks;
+  return a;
+}
+
+std::vector<GatherLaunch> build_gather_job(ArgTable& t, const std::vector<GatherProb>& p) {
+  std::vector<GatherLaunch> out;
+  std::vector<bool> used(p.size(), false);
+  for (size_t i = 0; i < p.size(); ++i) {
+    if (used[i]) continue;
+    GatherLaunch g;
+    g.plan = p[i].plan;
+    g.dtype = p[i].dtype;
+    std::vector<GatherArgs> args, rargs;
+    std::vector<uint32_t> cnt, rcnt;
+    for (size_t k = i; k < p.size(); ++k) {
+      const GatherPlan& q = p[k].plan;
+      if (used[k] || p[k].dtype != g.dtype || q.vec != g.plan.vec || q.lpr != g.plan.lpr ||
+          q.acc64 != g.plan.acc64)
+        continue;
+      used[k] = true;
+      args.push_back(p[k].args);
+      cnt.push_back(p[k].args.d * (uint32_t)q.nseg * (uint32_t)q.coltiles);
+      if (q.nseg > 1) {
+        rargs.push_back(p[k].args);
+        rcnt.push_back((uint32_t)p[k].args.red_blocks);
+      }
+    }
+    g.args = t.add(args.data(), args.size());
+    g.map = t.map(cnt, &g.items);
+    g.rargs = nullptr;
+    g.rmap = Map{nullptr, 0};
+    g.ritems = 0;
+    if (!rargs.empty()) {
+      g.rargs = t.add(rargs.data(), rargs.size());
+      g.rmap = t.map(rcnt, &g.ritems);
+    }
+    out.push_back(g);
+  }
+  return out;
+}
+
+sns_status launch_gather_job(const std::vector<GatherLaunch>& j, hipStream_t st) {
+  for (const GatherLaunch& g : j) {
+    if (g.dtype == SNS_F64) {
+      if (g.plan.vec == 2) dispatch_lpr<double, double, 2>(g, st);
+      else dispatch_lpr<double, double, 1>(g, st);
+    } else if (g.plan.acc64) {
+      if (g.plan.vec == 4) dispatch_lpr<float, double, 4>(g, st);
+      else dispatch_lpr<float, double, 1>(g, st);
+    } else {
+      if (g.plan.vec == 4) dispatch_lpr<float, float, 4>(g, st);
+      else dispatch_lpr<float, float, 1>(g, st);
+    }
   }
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;

@@ -316,7 +316,10 @@ CsrPlan make_csr_plan(const sns_matrix& A, uint32_t d, bool acc64) {
   return c;
 }
 
+constexpr size_t kCsrArgBytes = 4096;  // argument table of the row sort
+
 struct CsrBufs {
+  char* args;
   uint32_t* bcount;
   uint32_t* total;
   uint32_t* list;
@@ -328,6 +331,7 @@ struct CsrBufs {
 void carve_csr(Carve& c, const sns_matrix& A, uint32_t d, bool acc64, const CsrPlan& p,
                CsrBufs& b) {
   const size_t ab = acc64 ? 8 : 4;
+  b.args = c.take<char>(kCsrArgBytes);
   b.bcount = c.take<uint32_t>((size_t)p.nb + 1);
   b.total = c.take<uint32_t>(1);
   b.list = c.take<uint32_t>((size_t)A.m);
@@ -382,8 +386,13 @@ sns_status launch_csr_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, con
   SNS_LAUNCH("csr_scan", k_csr_scan, dim3(1), dim3(1024), 0, st, p.nb, bf.bcount, bf.total);
   SNS_LAUNCH("csr_compact", k_csr_compact, dim3(p.nb), dim3(kCompactThreads), 0, st, A.m,
              A.row_ptr, bf.bcount, bf.list);
-  sns_status s = launch_bucket_sort(p.sp, seed, nullptr, A.dtype, bf.sb, st, bf.list, bf.total);
+  ArgTable t(bf.args);
+  const std::vector<SortArgs> sa{sort_args(p.sp, seed, nullptr, bf.sb, bf.list, bf.total)};
+  const SortJob job = build_sort_job(t, sa, A.dtype == SNS_F64);
+  if (t.bytes() > kCsrArgBytes) return SNS_ERR_OUT_OF_MEMORY;
+  sns_status s = t.upload(st);
   if (s != SNS_OK) return s;
+  if ((s = launch_sort_job(job, st)) != SNS_OK) return s;
   if (A.dtype == SNS_F64) launch_csr_t<double, double>(A, d, seed, b, SA, Sb, p, bf, st);
   else if (a64) launch_csr_t<float, double>(A, d, seed, b, SA, Sb, p, bf, st);
   else launch_csr_t<float, float>(A, d, seed, b, SA, Sb, p, bf, st);

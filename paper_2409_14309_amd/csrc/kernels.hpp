@@ -1,9 +1,20 @@
 // Internal launchers of libsns (not part of the C ABI).
+//
+// Every kernel of the sort, CountSketch, QR and LSQR steps is batched: it
+// reads its per-problem arguments from a device-resident table, and work-group
+// g takes work item g, problem p owning items [off[p], off[p+1]).  A
+// single solve is a batch of one; a batch of uneven problems runs the same
+// kernels with the same per-problem arithmetic, so a problem's result does
+// not depend on what else is in the batch.  The host builds the argument
+// tables (ArgTable) and uploads them with a kernel launch, so a launch
+// sequence can be captured in a HIP graph.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
+
+#include <vector>
 
 #include "../../include/sns.h"
 
@@ -38,6 +49,56 @@ struct Carve {
   bool ok() const { return off <= cap; }
 };
 
+// ------------------------------------------------------------ batching ----
+// Work-item map of a batched launch (device pointers).
+struct Map {
+  const uint32_t* off;  // nprob + 1 entries; off[nprob] = total items
+  int nprob;
+};
+
+// Problem owning work item `item` (binary search; the value is uniform over
+// the work-group, so the loads are scalar).
+__device__ __forceinline__ int map_find(const Map& mp, uint32_t item) {
+  int lo = 0, hi = mp.nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (mp.off[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Work-groups to launch for `total` items: one per item (work-groups past
+// the last item return at once, so a launch may be sized for more).
+inline unsigned grid_for(uint32_t total) { return total ? total : 1u; }
+
+// Host builder of the device argument table.  Entries are appended to a host
+// image whose device location is known up front (dev may be null to size
+// it); upload() copies the image with kernel launches (no host memory is
+// referenced after it returns).
+class ArgTable {
+ public:
+  explicit ArgTable(void* dev = nullptr) : dev_(static_cast<char*>(dev)) {}
+  template <typename T>
+  T* add(const T* items, size_t count) {
+    const size_t off = reserve(sizeof(T) * count);
+    if (count) memcpy_bytes(off, items, sizeof(T) * count);
+    return reinterpret_cast<T*>(dev_ ? dev_ + off : nullptr);
+  }
+  // Offsets of a map from per-problem item counts; `total` receives the sum.
+  Map map(const std::vector<uint32_t>& counts, uint32_t* total);
+  size_t bytes() const { return host_.size(); }
+  sns_status upload(hipStream_t st) const;
+
+ private:
+  size_t reserve(size_t nbytes);
+  void memcpy_bytes(size_t off, const void* src, size_t nbytes);
+  std::vector<unsigned char> host_;
+  char* dev_;
+};
+// Alignment of the entries of an argument table (bytes).
+constexpr size_t kArgTableAlign = 16;
+
 // ---------------------------------------------------------------- sort ----
 // Stable counting sort of rows 0..m-1 by CountSketch bucket.  Produces
 // perm[m] (row id with the sign in bit 31, rows ascending inside a bucket),
@@ -47,7 +108,6 @@ struct SortPlan {
   uint32_t d = 0;
   int64_t rw = 0;       // rows per wave-block
   int64_t nwb = 0;      // wave-blocks
-  int waves = 1;        // waves per work-group in count/scatter
   int64_t seg = 64;     // wave-blocks per scan segment
   int64_t nseg = 0;     // scan segments
 };
@@ -60,19 +120,35 @@ struct SortBufs {
   uint32_t* segtot;
 };
 void carve_sort(Carve& c, const SortPlan& p, size_t b_elem_bytes, SortBufs& s);
-// rows (optional, ascending): sort rows[0..m) instead of 0..m-1; b is then
-// indexed by the row id.  mdev (optional): device-side key count <= p.m.
-sns_status launch_bucket_sort(const SortPlan& p, uint64_t seed, const void* b, sns_dtype bt,
-                              const SortBufs& s, hipStream_t st, const uint32_t* rows = nullptr,
-                              const uint32_t* mdev = nullptr);
-
-// ------------------------------------------------------------------ CSR ----
-// CountSketch of a CSR matrix: SA (d x n, A's dtype) and, when b is given,
-// Sb (d).  Deterministic; see csr.hip.
-size_t csr_workspace_bytes(const sns_matrix& A, uint32_t d, bool acc64);
-sns_status launch_csr_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
-                             void* SA, void* Sb, bool acc64, void* ws, size_t ws_bytes,
-                             hipStream_t st);
+// One problem's sort.  rows (optional, ascending): sort rows[0..m) instead of
+// 0..m-1; b is then indexed by the row id.  mdev (optional): device-side key
+// count <= m.
+struct SortArgs {
+  uint64_t seed;
+  int64_t m, rw, nwb, seg, nseg;
+  uint32_t d;
+  const uint32_t* rows;
+  const uint32_t* mdev;
+  const void* b;
+  uint32_t* perm;
+  void* bperm;
+  uint32_t* bucket_ptr;
+  uint32_t* counts;
+  uint32_t* segtot;
+};
+SortArgs sort_args(const SortPlan& p, uint64_t seed, const void* b, const SortBufs& s,
+                   const uint32_t* rows = nullptr, const uint32_t* mdev = nullptr);
+// A batched sort launch sequence (all problems share b's element type).
+struct SortJob {
+  const SortArgs* args = nullptr;
+  Map mcount{}, mseg{}, mscan{};
+  uint32_t ncount = 0, nseg = 0, nscan = 0;
+  uint32_t maxd = 1;
+  bool f64 = false;
+  int count = 0;
+};
+SortJob build_sort_job(ArgTable& t, const std::vector<SortArgs>& a, bool f64);
+sns_status launch_sort_job(const SortJob& j, hipStream_t st);
 sns_status launch_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uint32_t* h,
                        int8_t* s, hipStream_t st);
 
@@ -83,9 +159,46 @@ struct GatherPlan {
 };
 GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64);
 size_t gather_partial_bytes(const GatherPlan& g, const sns_matrix& A, uint32_t d);
-sns_status launch_cs_gather(const GatherPlan& g, const sns_matrix& A, uint32_t d,
-                            const SortBufs& s, bool with_b, void* SA, void* Sb, void* part,
-                            hipStream_t st);
+struct GatherArgs {
+  const void* A;
+  int64_t ld;
+  int n, nseg, coltiles, red_blocks;
+  uint32_t d;
+  const uint32_t* perm;
+  const void* bperm;  // null: no Sb
+  const uint32_t* bucket_ptr;
+  void* SA;
+  void* Sb;
+  void* partA;
+  void* partB;
+};
+GatherArgs gather_args(const GatherPlan& g, const sns_matrix& A, uint32_t d, const SortBufs& s,
+                       bool with_b, void* SA, void* Sb, void* part);
+struct GatherProb {  // host-side pairing of a plan with its arguments
+  GatherPlan plan;
+  GatherArgs args;
+  sns_dtype dtype;
+};
+struct GatherLaunch {
+  GatherPlan plan;  // class (vec, lpr, acc64) shared by the launch
+  sns_dtype dtype;
+  const GatherArgs* args;
+  Map map;
+  uint32_t items;
+  const GatherArgs* rargs;  // problems with segment partials
+  Map rmap;
+  uint32_t ritems;
+};
+std::vector<GatherLaunch> build_gather_job(ArgTable& t, const std::vector<GatherProb>& p);
+sns_status launch_gather_job(const std::vector<GatherLaunch>& j, hipStream_t st);
+
+// ------------------------------------------------------------------ CSR ----
+// CountSketch of a CSR matrix: SA (d x n, A's dtype) and, when b is given,
+// Sb (d).  Deterministic; see csr.hip.
+size_t csr_workspace_bytes(const sns_matrix& A, uint32_t d, bool acc64);
+sns_status launch_csr_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
+                             void* SA, void* Sb, bool acc64, void* ws, size_t ws_bytes,
+                             hipStream_t st);
 
 // ------------------------------------------------------------------- QR ----
 struct QrBufs {
@@ -101,10 +214,43 @@ struct QrBufs {
 size_t qr_workspace_bytes(int64_t d, int64_t n);
 void carve_qr(Carve& c, int64_t d, int64_t n, QrBufs& q);
 // Factor [SA | Sb] and solve R x0 = c.  Writes x0 (fp64 n) and, if Rout is
-// set, R row-major.  info_dev (device sns_info) gets status and sketch_resid.
-sns_status launch_qr_solve(int64_t d, int64_t n, sns_dtype dt, const void* SA, int64_t ld_sa,
-                           const void* Sb, const QrBufs& q, double* x0, double* Rout,
-                           sns_info* info_dev, hipStream_t st);
+// set, R row-major.  info (device sns_info) gets status and sketch_resid.
+struct QrArgs {
+  int64_t d, n, ld_sa;
+  const void* SA;
+  const void* Sb;
+  double* M;
+  double* T;
+  double* tau;
+  double* R;
+  double* Rr;
+  double* invd;
+  double* x0;
+  double* Rout;
+  double* scal;
+  sns_info* info;
+};
+QrArgs qr_args(int64_t d, int64_t n, const void* SA, int64_t ld_sa, const void* Sb,
+               const QrBufs& q, double* x0, double* Rout, sns_info* info);
+struct QrJob {
+  bool f64 = false;  // SA element type
+  const QrArgs* all = nullptr;
+  Map mload{}, mone{};
+  uint32_t nload = 0;
+  int count = 0;
+  int64_t maxn = 0;
+  struct Cls {
+    int cfg;  // panel configuration index
+    const QrArgs* args;
+    Map mone, mtrail;
+    uint32_t ntrail;
+    int count;
+    int64_t maxn;
+  };
+  std::vector<Cls> cls;
+};
+QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64);
+sns_status launch_qr_job(const QrJob& j, hipStream_t st);
 
 // ----------------------------------------------------------------- LSQR ----
 struct LsqrState;  // device-resident scalars, defined in lsqr.hip
@@ -129,12 +275,67 @@ struct LsqrPlan {
 LsqrPlan make_lsqr_plan(const sns_matrix& A);
 size_t lsqr_workspace_bytes(const sns_matrix& A, const LsqrPlan& p);
 void carve_lsqr(Carve& c, const sns_matrix& A, const LsqrPlan& p, LsqrBufs& l);
-// SAP-SAS refinement: LSQR on A R^{-1} from r0 = b - A x0.  R is the n x n
-// column-major factor in q.R; x0 in q.xw.  Writes x (fp64 n) and updates
-// info_dev (iters, rel_resid_est, status).
-sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan& p,
-                             const LsqrBufs& l, const QrBufs& q, int d, int max_iters,
-                             double rtol, double* x, sns_info* info_dev, hipStream_t st);
+struct LsqrArgs {
+  const void* A;
+  int64_t ld, m;
+  int n, grid, max_iters;
+  const void* b;
+  void* u;
+  double* zpart;
+  double* npart;
+  double* zred2;
+  double* nred2;
+  double* Xc;
+  double* Xr;
+  double* ypart;
+  double* vecs;
+  LsqrState* st;
+  const double* Rc;
+  const double* invd;
+  const double* x0;
+  double* x;
+  sns_info* info;
+  double sighat, stop;
+};
+// SAP-SAS refinement of one problem: LSQR on A R^{-1} from r0 = b - A x0.  R
+// is the n x n column-major factor in q.R; x0 in q.xw.  Writes x (fp64 n) and
+// updates info (iters, rel_resid_est, status).
+LsqrArgs lsqr_args(const sns_matrix& A, const void* b, const LsqrPlan& p, const LsqrBufs& l,
+                   const QrBufs& q, int d, int max_iters, double rtol, double* x,
+                   sns_info* info);
+struct LsqrProb {
+  LsqrPlan plan;
+  LsqrArgs args;
+};
+struct LsqrJob {
+  bool f64 = false;
+  const LsqrArgs* all = nullptr;
+  Map mone{}, minv{}, mred{}, mgemv{};
+  uint32_t ninv = 0, nred = 0, ngemv = 0;
+  int count = 0;
+  int maxn = 0;
+  struct Cls {
+    LsqrPlan plan;  // lpr, nch, unroll of the class
+    const LsqrArgs* args;
+    Map map;
+    uint32_t items;
+  };
+  std::vector<Cls> cls;
+  // single problem: its device state and stop threshold, for host polling
+  const LsqrState* state = nullptr;
+  double stop = 0.0, sighat = 0.0;
+};
+LsqrJob build_lsqr_job(ArgTable& t, const std::vector<LsqrProb>& p, bool f64);
+// Set-up (X = R^{-1}, state), as many iterations as needed (single problem:
+// host polling of the stop flag; several problems: `max_iters` of them,
+// finished problems skipping), the final update and the report.
+sns_status launch_lsqr_setup(const LsqrJob& j, hipStream_t st);
+sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t st);
+sns_status launch_lsqr_finish(const LsqrJob& j, hipStream_t st);
+sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipStream_t st);
+// Number of problems of the job that have not stopped, written to *out
+// (device int) on the stream.
+sns_status launch_lsqr_active(const LsqrJob& j, int* out, hipStream_t st);
 
 // ------------------------------------------------------------- Gaussian ----
 const uint16_t* gauss_table_host();

@@ -80,23 +80,28 @@ __device__ __forceinline__ void load_row_chunks(const T* __restrict__ row, int l
   }
 }
 
-// Fused pass: for each row i of this work-group's contiguous row range,
+// Fused pass over one work item (a contiguous row range of one problem): for
+// each row i,
 //   t = A[i,:] . w;  u'[i] = t - gamma * uin[i];  z += A[i,:]^T u'[i];
-//   nrm += u'[i]^2.  Per-group z and nrm go to zpart / npart.  A row is
-// spread over LPR lanes (NCH 16-byte chunks each); each row slot handles two
-// rows per step so that two rows' loads are in flight together.
+//   nrm += u'[i]^2.  Per-item z and nrm go to zpart / npart.  A row is spread
+// over LPR lanes (NCH 16-byte chunks each).  uin is b before the first step
+// (the residual pass) and u afterwards.
 template <typename T, int VEC, int LPR, int NCH, int U>
-__global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(
-    const T* __restrict__ A, int64_t ld, int64_t m, int n, const LsqrState* __restrict__ st,
-    const double* __restrict__ wv, const T* __restrict__ uin, T* __restrict__ uout,
-    double* __restrict__ zpart, double* __restrict__ npart) {
+__device__ __forceinline__ void lsqr_pass_item(const LsqrArgs& a, uint32_t loc, double* zred_,
+                                               double* nred) {
   constexpr int RPW = 64 / LPR;
   constexpr int CW = LPR * VEC;          // columns per chunk
   constexpr int NSL = kPassWaves * RPW;  // row slots per group
-  __shared__ double zred[kPassWaves][NCH * CW];
-  __shared__ double nred[kPassWaves];
+  double (*zred)[NCH * CW] = reinterpret_cast<double (*)[NCH * CW]>(zred_);
+  const LsqrState* __restrict__ st = a.st;
   if (st->done) return;
   const double gamma = st->gamma;
+  const T* __restrict__ A = static_cast<const T*>(a.A);
+  const T* __restrict__ uin = static_cast<const T*>(st->iter < 0 ? a.b : a.u);
+  T* __restrict__ uout = static_cast<T*>(a.u);
+  const double* __restrict__ wv = a.vecs;  // w_pass
+  const int64_t ld = a.ld, m = a.m;
+  const int n = a.n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int slot = wid * RPW + lane / LPR, lr = lane % LPR;
 
@@ -111,8 +116,8 @@ __global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(
     }
   double nrm = 0.0;
 
-  const int64_t r0 = m * (int64_t)blockIdx.x / gridDim.x;
-  const int64_t r1 = m * (int64_t)(blockIdx.x + 1) / gridDim.x;
+  const int64_t r0 = m * (int64_t)loc / a.grid;
+  const int64_t r1 = m * (int64_t)(loc + 1) / a.grid;
   if constexpr (U == 1) {
     for (int64_t i = r0 + slot; i < r1; i += NSL) {
       T a0[NCH][VEC];
@@ -203,35 +208,44 @@ __global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < kPassWaves; ++q) s += zred[q][col];
-    zpart[(size_t)blockIdx.x * n + col] = s;
+    a.zpart[(size_t)loc * n + col] = s;
   }
   if (threadIdx.x == 0) {
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < kPassWaves; ++q) s += nred[q];
-    npart[blockIdx.x] = s;
+    a.npart[loc] = s;
   }
 }
 
-// First level of the reduction of the G per-group partials: work-group
-// (cx, s) sums partials [s G / S, (s+1) G / S) for columns [64 cx, 64 cx + 64)
-// into zred2[s][.] (and, for cx = 0, the norms into nred2[s]).  Four thread
-// groups take every fourth partial, each with eight running sums (partials
-// g, g + 4, ..., g + 28 of a round of 32); all sums are combined in a fixed
+template <typename T, int VEC, int LPR, int NCH, int U>
+__global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(const LsqrArgs* __restrict__ P,
+                                                               Map mp) {
+  constexpr int CW = LPR * VEC;
+  __shared__ double zred[kPassWaves * NCH * CW];
+  __shared__ double nred[kPassWaves];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  lsqr_pass_item<T, VEC, LPR, NCH, U>(P[pi], it - mp.off[pi], zred, nred);
+}
+
+// First level of the reduction of the G per-group partials: item (cx, s)
+// sums partials [s G / S, (s+1) G / S) for columns [64 cx, 64 cx + 64) into
+// zred2[s][.] (and, for cx = 0, the norms into nred2[s]).  Four thread groups
+// take every fourth partial, each with eight running sums (partials g,
+// g + 4, ..., g + 28 of a round of 32); all sums are combined in a fixed
 // order.
-__global__ __launch_bounds__(256) void k_lsqr_reduce(int n, int G,
-                                                     const LsqrState* __restrict__ st,
-                                                     const double* __restrict__ zpart,
-                                                     const double* __restrict__ npart,
-                                                     double* __restrict__ zred2,
-                                                     double* __restrict__ nred2) {
-  __shared__ double part[4][64];
-  __shared__ double red[4];
-  if (st->done) return;
+__device__ __forceinline__ void lsqr_reduce_item(const LsqrArgs& a, uint32_t loc,
+                                                 double (*part)[64], double* red) {
+  if (a.st->done) return;
+  const int n = a.n, G = a.grid;
+  const uint32_t cxn = (uint32_t)((n + 63) / 64);
+  const int cx = (int)(loc % cxn), s = (int)(loc / cxn);
   const int t = threadIdx.x, cl = t & 63, grp = t >> 6;
-  const int s = blockIdx.y;
   const int g0 = (int)((int64_t)G * s / kRedSplit), g1 = (int)((int64_t)G * (s + 1) / kRedSplit);
-  const int col = blockIdx.x * 64 + cl;
+  const int col = cx * 64 + cl;
+  const double* __restrict__ zpart = a.zpart;
   double acc[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[k] = 0.0;
@@ -248,59 +262,76 @@ __global__ __launch_bounds__(256) void k_lsqr_reduce(int n, int G,
   }
   part[grp][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
-  if (t < 64 && col < n) zred2[(size_t)s * n + col] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
-  if (blockIdx.x == 0) {
-    double a = 0.0;
-    for (int g = g0 + t; g < g1; g += 256) a += npart[g];
-    a = block_sum(a, red);
-    if (t == 0) nred2[s] = a;
+  if (t < 64 && col < n)
+    a.zred2[(size_t)s * n + col] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+  if (cx == 0) {
+    double q = 0.0;
+    for (int g = g0 + t; g < g1; g += 256) q += a.npart[g];
+    q = block_sum(q, red);
+    if (t == 0) a.nred2[s] = q;
   }
 }
 
-__global__ void k_lsqr_init(int n, int max_iters, double stop, LsqrState* st,
-                            const double* __restrict__ x0, double* __restrict__ wpass,
-                            double* __restrict__ dy) {
+__global__ __launch_bounds__(256) void k_lsqr_reduce(const LsqrArgs* __restrict__ P, Map mp) {
+  __shared__ double part[4][64];
+  __shared__ double red[4];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  lsqr_reduce_item(P[pi], it - mp.off[pi], part, red);
+}
+
+__global__ void k_lsqr_init(const LsqrArgs* __restrict__ P, Map mp) {
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const LsqrArgs& a = P[map_find(mp, it)];
+  const int n = a.n;
+  double* wpass = a.vecs;
+  double* dy = a.vecs + 3 * n;
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
-    wpass[j] = -x0[j];
+    wpass[j] = -a.x0[j];
     dy[j] = 0.0;
   }
   if (threadIdx.x == 0) {
+    LsqrState* st = a.st;
     st->alpha = st->beta = st->rhobar = st->phibar = 0.0;
     st->gamma = -1.0;
     st->ratio = 0.0;
-    st->stop = stop;
+    st->stop = a.stop;
     st->iter = -1;  // the next step consumes the residual pass
-    st->max_iters = max_iters;
-    st->done = max_iters <= 0 ? 1 : 0;
+    st->max_iters = a.max_iters;
+    st->done = a.max_iters <= 0 ? 1 : 0;
     st->status = SNS_OK;
     st->arrived = 0u;
   }
 }
 
-// X = R^{-1}: work-group j solves R x = e_j on the leading (j+1) x (j+1)
-// block by back substitution and writes column j of X (column-major Xc and
-// row-major Xr; X is upper triangular).
+// X = R^{-1}: item j solves R x = e_j on the leading (j+1) x (j+1) block by
+// back substitution and writes column j of X (column-major Xc and row-major
+// Xr; X is upper triangular).
 constexpr int kInvThreads = 64;
-__global__ __launch_bounds__(kInvThreads) void k_tri_inv(int n, const double* __restrict__ Rc,
-                                                         const double* __restrict__ invd,
-                                                         double* __restrict__ Xc,
-                                                         double* __restrict__ Xr) {
+__global__ __launch_bounds__(kInvThreads) void k_tri_inv(const LsqrArgs* __restrict__ P, Map mp) {
   extern __shared__ double sh[];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  const LsqrArgs& a = P[pi];
+  const int n = a.n;
+  const int j = (int)(it - mp.off[pi]);
   double* x = sh;        // n
   double* blk = sh + n;  // 64 x 64
-  const int j = blockIdx.x;
   for (int i = threadIdx.x; i < n; i += kInvThreads) x[i] = i == j ? 1.0 : 0.0;
   __syncthreads();
-  trsv_lds<true, kInvThreads>(Rc, n, j + 1, invd, x, blk);
+  trsv_lds<true, kInvThreads>(a.Rc, n, j + 1, a.invd, x, blk);
   for (int i = threadIdx.x; i < n; i += kInvThreads) {
     const double v = i <= j ? x[i] : 0.0;
-    Xc[(int64_t)j * n + i] = v;
-    Xr[(int64_t)i * n + j] = v;
+    a.Xc[(int64_t)j * n + i] = v;
+    a.Xr[(int64_t)i * n + j] = v;
   }
 }
 
 constexpr int kGemvThreads = 256;
-constexpr int kGemvRows = 16;  // rows per work-group (4 per wave)
+constexpr int kGemvRows = 16;  // rows per work item (4 per wave)
 
 // Dot product of row i of a triangular matrix stored row-contiguously
 // (M[i * n + j]) with vec over j in [j0, j1), by one wave; all lanes get it.
@@ -315,36 +346,39 @@ __device__ __forceinline__ double wave_row_dot(const double* __restrict__ M, int
 
 // y = X^T (z / beta) - beta v (first step: X^T (z / beta)), z = sum of the
 // reduction splits.  X^T row i = X column i = Xc[i * n + j], j <= i.  Each
-// group writes its rows of y and its share of ||y||^2; the last group to
-// finish (arrival counter) then runs the scalar recurrences and the n-vector
-// updates for the whole vector in a fixed order.
-__global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(
-    int n, double sighat, const double* __restrict__ Xc, const double* __restrict__ zred2,
-    const double* __restrict__ nred2, LsqrState* __restrict__ st, double* __restrict__ zbuf,
-    double* __restrict__ ybuf, double* __restrict__ ypart, double* __restrict__ v,
-    double* __restrict__ wd, double* __restrict__ dy) {
-  extern __shared__ double sh[];
+// item writes its rows of y and its share of ||y||^2; the last item of the
+// problem to finish (arrival counter) then runs the scalar recurrences and
+// the n-vector updates for the whole vector in a fixed order.
+__device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, double* sh,
+                                              bool* last) {
+  LsqrState* __restrict__ st = a.st;
+  if (st->done) return;
+  const int n = a.n;
+  const double sighat = a.sighat;
+  const uint32_t nitems = (uint32_t)((n + kGemvRows - 1) / kGemvRows);
   double* z = sh;        // n
   double* red = sh + n;  // 16 + kGemvRows
-  __shared__ bool last;
-  if (st->done) return;
+  double* v = a.vecs + n;
+  double* wd = a.vecs + 2 * n;
+  double* dy = a.vecs + 3 * n;
+  double* ybuf = a.vecs + 4 * n;
   const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
   double beta2 = 0.0;
-  for (int s = 0; s < kRedSplit; ++s) beta2 += nred2[s];
+  for (int s = 0; s < kRedSplit; ++s) beta2 += a.nred2[s];
   const double beta = sqrt(beta2);
   const double invb = beta > 0.0 ? 1.0 / beta : 0.0;
   const bool first = st->iter < 0;
   for (int j = t; j < n; j += nt) {
-    double a = 0.0;
-    for (int s = 0; s < kRedSplit; ++s) a += zred2[(size_t)s * n + j];
-    z[j] = a * invb;
+    double q = 0.0;
+    for (int s = 0; s < kRedSplit; ++s) q += a.zred2[(size_t)s * n + j];
+    z[j] = q * invb;
   }
   __syncthreads();
   double ysq = 0.0;
   for (int r = wv; r < kGemvRows; r += nt / 64) {
-    const int i = blockIdx.x * kGemvRows + r;
+    const int i = (int)loc * kGemvRows + r;
     if (i < n) {
-      double yi = wave_row_dot(Xc, n, i, 0, i + 1, z);
+      double yi = wave_row_dot(a.Xc, n, i, 0, i + 1, z);
       if (!first) yi -= beta * v[i];
       if (lane == 0) {
         ybuf[i] = yi;
@@ -357,19 +391,20 @@ __global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(
   __syncthreads();
   if (t == 0) {
     for (int r = 0; r < kGemvRows; ++r) ysq += red[16 + r];
-    ypart[blockIdx.x] = ysq;
+    a.ypart[loc] = ysq;
     __threadfence();
     const unsigned int prev = atomicAdd(&st->arrived, 1u);
-    last = prev == gridDim.x - 1;
+    *last = prev == nitems - 1;
   }
   __syncthreads();
-  if (!last) return;
+  if (!*last) return;
   __threadfence();
-  // ---- last group: scalars and n-vector updates ----
+  // ---- last item: scalars and n-vector updates ----
   double a2 = 0.0;
-  for (int g = 0; g < (int)gridDim.x; ++g) a2 += ypart[g];  // same value on every thread
+  for (uint32_t g = 0; g < nitems; ++g) a2 += a.ypart[g];  // same value on every thread
   const double alpha = sqrt(a2);
   if (!isfinite(beta) || !isfinite(alpha)) {
+    __syncthreads();
     if (t == 0) {
       st->status = SNS_ERR_NUMERICAL;
       st->done = 1;
@@ -386,6 +421,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(
       wd[j] = vj;
       dy[j] = 0.0;
     }
+    __syncthreads();
     if (t == 0) {
       st->beta = beta;
       st->alpha = alpha;
@@ -410,6 +446,7 @@ __global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(
       wd[j] = vj - f2 * wdj;
       v[j] = vj;
     }
+    __syncthreads();
     if (t == 0) {
       st->beta = beta;
       st->alpha = alpha;
@@ -431,71 +468,97 @@ __global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(
   if (t == 0) st->arrived = 0u;
 }
 
-// w = X v for the next pass: row i of X = Xr[i * n + j], j >= i.  `out`
-// receives w; with add0 set, out = add0 + X v (the final x = x0 + X dy).
-__global__ __launch_bounds__(kGemvThreads) void k_lsqr_xv(int n, const double* __restrict__ Xr,
-                                                          const double* __restrict__ vin,
-                                                          const double* __restrict__ add0,
-                                                          const LsqrState* __restrict__ st,
-                                                          int skip_if_done,
-                                                          double* __restrict__ out) {
+__global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(const LsqrArgs* __restrict__ P,
+                                                           Map mp) {
   extern __shared__ double sh[];
-  double* vec = sh;  // n
-  if (skip_if_done && st->done) return;
+  __shared__ bool last;
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  lsqr_xtz_item(P[pi], it - mp.off[pi], sh, &last);
+}
+
+// mode 0: w_pass = X v for the next pass (skipped once the problem stopped);
+// mode 1: x = x0 + X dy.  Row i of X = Xr[i * n + j], j >= i.
+__device__ __forceinline__ void lsqr_xv_item(const LsqrArgs& a, uint32_t loc, int mode,
+                                             double* vec) {
+  if (mode == 0 && a.st->done) return;
+  const int n = a.n;
+  const double* vin = mode == 0 ? a.vecs + n : a.vecs + 3 * n;
+  double* out = mode == 0 ? a.vecs : a.x;
+  const double* add0 = mode == 0 ? nullptr : a.x0;
   const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
   for (int j = t; j < n; j += nt) vec[j] = vin[j];
   __syncthreads();
   for (int r = wv; r < kGemvRows; r += nt / 64) {
-    const int i = blockIdx.x * kGemvRows + r;
+    const int i = (int)loc * kGemvRows + r;
     if (i < n) {
-      const double wi = wave_row_dot(Xr, n, i, i, n, vec);
+      const double wi = wave_row_dot(a.Xr, n, i, i, n, vec);
       if (lane == 0) out[i] = add0 ? add0[i] + wi : wi;
     }
   }
 }
 
-__global__ void k_lsqr_report(const LsqrState* __restrict__ st, sns_info* __restrict__ info) {
+__global__ __launch_bounds__(kGemvThreads) void k_lsqr_xv(const LsqrArgs* __restrict__ P, Map mp,
+                                                          int mode) {
+  extern __shared__ double sh[];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  lsqr_xv_item(P[pi], it - mp.off[pi], mode, sh);
+}
+
+__global__ void k_lsqr_report(const LsqrArgs* __restrict__ P, Map mp) {
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const LsqrArgs& a = P[map_find(mp, it)];
+  if (threadIdx.x != 0) return;
+  const LsqrState* st = a.st;
+  sns_info* info = a.info;
   info->iters = st->iter < 0 ? 0 : st->iter;
   info->rel_resid_est = st->ratio;
   if (info->status == SNS_OK) info->status = st->status;
 }
 
+// Number of problems not yet stopped.
+__global__ void k_lsqr_active(const LsqrArgs* __restrict__ P, int nprob, int* __restrict__ out) {
+  __shared__ int red[4];
+  int c = 0;
+  for (int p = threadIdx.x; p < nprob; p += blockDim.x) c += P[p].st->done ? 0 : 1;
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) *out = c;
+}
+
 template <typename T, int VEC, int LPR, int NCH, int U>
-void launch_pass_t(const sns_matrix& A, const LsqrPlan& p, const LsqrBufs& l, const void* uin,
-                   hipStream_t s) {
-  double* vecs = l.vecs;
-  SNS_LAUNCH("lsqr_pass", (k_lsqr_pass<T, VEC, LPR, NCH, U>), dim3(p.grid), dim3(kPassWaves * 64),
-             0, s, static_cast<const T*>(A.values), A.ld, A.m, (int)A.n,
-             static_cast<const LsqrState*>(l.state), vecs, static_cast<const T*>(uin),
-             static_cast<T*>(l.u), l.zpart, l.npart);
+void launch_pass_t(const LsqrJob::Cls& c, hipStream_t s) {
+  SNS_LAUNCH("lsqr_pass", (k_lsqr_pass<T, VEC, LPR, NCH, U>), dim3(grid_for(c.items)),
+             dim3(kPassWaves * 64), 0, s, c.args, c.map);
 }
 
 template <typename T, int VEC, int U>
-void launch_pass_u(const sns_matrix& A, const LsqrPlan& p, const LsqrBufs& l, const void* uin,
-                   hipStream_t s) {
-  switch (p.lpr * 16 + p.nch) {
-    case 4 * 16 + 1: launch_pass_t<T, VEC, 4, 1, U>(A, p, l, uin, s); break;
-    case 4 * 16 + 2: launch_pass_t<T, VEC, 4, 2, U>(A, p, l, uin, s); break;
-    case 4 * 16 + 4: launch_pass_t<T, VEC, 4, 4, U>(A, p, l, uin, s); break;
-    case 8 * 16 + 4: launch_pass_t<T, VEC, 8, 4, U>(A, p, l, uin, s); break;
-    case 16 * 16 + 1: launch_pass_t<T, VEC, 16, 1, U>(A, p, l, uin, s); break;
-    case 16 * 16 + 2: launch_pass_t<T, VEC, 16, 2, U>(A, p, l, uin, s); break;
-    case 16 * 16 + 4: launch_pass_t<T, VEC, 16, 4, U>(A, p, l, uin, s); break;
-    case 32 * 16 + 1: launch_pass_t<T, VEC, 32, 1, U>(A, p, l, uin, s); break;
-    case 32 * 16 + 2: launch_pass_t<T, VEC, 32, 2, U>(A, p, l, uin, s); break;
-    case 32 * 16 + 4: launch_pass_t<T, VEC, 32, 4, U>(A, p, l, uin, s); break;
-    case 64 * 16 + 1: launch_pass_t<T, VEC, 64, 1, U>(A, p, l, uin, s); break;
-    case 64 * 16 + 2: launch_pass_t<T, VEC, 64, 2, U>(A, p, l, uin, s); break;
-    case 64 * 16 + 4: launch_pass_t<T, VEC, 64, 4, U>(A, p, l, uin, s); break;
-    default: launch_pass_t<T, VEC, 64, 8, U>(A, p, l, uin, s); break;
+void launch_pass_u(const LsqrJob::Cls& c, hipStream_t s) {
+  switch (c.plan.lpr * 16 + c.plan.nch) {
+    case 4 * 16 + 1: launch_pass_t<T, VEC, 4, 1, U>(c, s); break;
+    case 4 * 16 + 2: launch_pass_t<T, VEC, 4, 2, U>(c, s); break;
+    case 4 * 16 + 4: launch_pass_t<T, VEC, 4, 4, U>(c, s); break;
+    case 8 * 16 + 4: launch_pass_t<T, VEC, 8, 4, U>(c, s); break;
+    case 16 * 16 + 1: launch_pass_t<T, VEC, 16, 1, U>(c, s); break;
+    case 16 * 16 + 2: launch_pass_t<T, VEC, 16, 2, U>(c, s); break;
+    case 16 * 16 + 4: launch_pass_t<T, VEC, 16, 4, U>(c, s); break;
+    case 32 * 16 + 1: launch_pass_t<T, VEC, 32, 1, U>(c, s); break;
+    case 32 * 16 + 2: launch_pass_t<T, VEC, 32, 2, U>(c, s); break;
+    case 32 * 16 + 4: launch_pass_t<T, VEC, 32, 4, U>(c, s); break;
+    case 64 * 16 + 1: launch_pass_t<T, VEC, 64, 1, U>(c, s); break;
+    case 64 * 16 + 2: launch_pass_t<T, VEC, 64, 2, U>(c, s); break;
+    case 64 * 16 + 4: launch_pass_t<T, VEC, 64, 4, U>(c, s); break;
+    default: launch_pass_t<T, VEC, 64, 8, U>(c, s); break;
   }
 }
 
 template <typename T, int VEC>
-void launch_pass_v(const sns_matrix& A, const LsqrPlan& p, const LsqrBufs& l, const void* uin,
-                   hipStream_t s) {
-  if (p.unroll == 2) launch_pass_u<T, VEC, 2>(A, p, l, uin, s);
-  else launch_pass_u<T, VEC, 1>(A, p, l, uin, s);
+void launch_pass_v(const LsqrJob::Cls& c, hipStream_t s) {
+  if (c.plan.unroll == 2) launch_pass_u<T, VEC, 2>(c, s);
+  else launch_pass_u<T, VEC, 1>(c, s);
 }
 
 }  // namespace
@@ -559,6 +622,128 @@ void carve_lsqr(Carve& c, const sns_matrix& A, const LsqrPlan& p, LsqrBufs& l) {
   l.state = c.take<LsqrState>(1);
 }
 
+LsqrArgs lsqr_args(const sns_matrix& A, const void* b, const LsqrPlan& p, const LsqrBufs& l,
+                   const QrBufs& q, int d, int max_iters, double rtol, double* x,
+                   sns_info* info) {
+  LsqrArgs a;
+  const int n = (int)A.n;
+  a.A = A.values;
+  a.ld = A.ld;
+  a.m = A.m;
+  a.n = n;
+  a.grid = p.grid;
+  a.max_iters = max_iters;
+  a.b = b;
+  a.u = l.u;
+  a.zpart = l.zpart;
+  a.npart = l.npart;
+  a.zred2 = l.zred2;
+  a.nred2 = l.nred2;
+  a.Xc = l.Xc;
+  a.Xr = l.Xr;
+  a.ypart = l.ypart;
+  a.vecs = l.vecs;
+  a.st = static_cast<LsqrState*>(l.state);
+  a.Rc = q.R;
+  a.invd = q.invd;
+  a.x0 = q.xw;
+  a.x = x;
+  a.info = info;
+  a.sighat = 1.0 - sqrt((double)n / (double)d);
+  a.stop = rtol > 0.0 ? rtol * (a.sighat > 0.0 ? a.sighat : 1.0) : 0.0;
+  return a;
+}
+
+LsqrJob build_lsqr_job(ArgTable& t, const std::vector<LsqrProb>& p, bool f64) {
+  LsqrJob j;
+  j.f64 = f64;
+  j.count = (int)p.size();
+  if (p.empty()) return j;
+  std::vector<LsqrArgs> all;
+  std::vector<uint32_t> one, inv, red, gemv;
+  for (const LsqrProb& x : p) {
+    all.push_back(x.args);
+    const int n = x.args.n;
+    one.push_back(1u);
+    inv.push_back((uint32_t)n);
+    red.push_back((uint32_t)(((n + 63) / 64) * kRedSplit));
+    gemv.push_back((uint32_t)((n + kGemvRows - 1) / kGemvRows));
+    j.maxn = n > j.maxn ? n : j.maxn;
+  }
+  j.all = t.add(all.data(), all.size());
+  uint32_t tmp = 0;
+  j.mone = t.map(one, &tmp);
+  j.minv = t.map(inv, &j.ninv);
+  j.mred = t.map(red, &j.nred);
+  j.mgemv = t.map(gemv, &j.ngemv);
+  std::vector<bool> used(p.size(), false);
+  for (size_t i = 0; i < p.size(); ++i) {
+    if (used[i]) continue;
+    LsqrJob::Cls c;
+    c.plan = p[i].plan;
+    std::vector<LsqrArgs> sub;
+    std::vector<uint32_t> cnt;
+    for (size_t k = i; k < p.size(); ++k) {
+      const LsqrPlan& q = p[k].plan;
+      if (used[k] || q.lpr != c.plan.lpr || q.nch != c.plan.nch || q.unroll != c.plan.unroll)
+        continue;
+      used[k] = true;
+      sub.push_back(p[k].args);
+      cnt.push_back((uint32_t)p[k].args.grid);
+    }
+    c.args = t.add(sub.data(), sub.size());
+    c.map = t.map(cnt, &c.items);
+    j.cls.push_back(c);
+  }
+  if (p.size() == 1) {
+    j.state = p[0].args.st;
+    j.stop = p[0].args.stop;
+    j.sighat = p[0].args.sighat;
+  }
+  return j;
+}
+
+sns_status launch_lsqr_setup(const LsqrJob& j, hipStream_t s) {
+  if (j.count == 0) return SNS_OK;
+  SNS_LAUNCH("lsqr_init", k_lsqr_init, dim3(grid_for((uint32_t)j.count)), dim3(256), 0, s, j.all,
+             j.mone);
+  SNS_LAUNCH("tri_inv", k_tri_inv, dim3(grid_for(j.ninv)), dim3(kInvThreads),
+             ((size_t)j.maxn + 4096) * sizeof(double), s, j.all, j.minv);
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
+}
+
+sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t s) {
+  if (j.count == 0) return SNS_OK;
+  for (const LsqrJob::Cls& c : j.cls) {
+    if (j.f64) launch_pass_v<double, 2>(c, s);
+    else launch_pass_v<float, 4>(c, s);
+  }
+  SNS_LAUNCH("lsqr_reduce", k_lsqr_reduce, dim3(grid_for(j.nred)), dim3(256), 0, s, j.all, j.mred);
+  SNS_LAUNCH("lsqr_xtz", k_lsqr_xtz, dim3(grid_for(j.ngemv)), dim3(kGemvThreads),
+             ((size_t)j.maxn + 16 + kGemvRows) * sizeof(double), s, j.all, j.mgemv);
+  SNS_LAUNCH("lsqr_xv", k_lsqr_xv, dim3(grid_for(j.ngemv)), dim3(kGemvThreads),
+             (size_t)j.maxn * sizeof(double), s, j.all, j.mgemv, 0);
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
+}
+
+sns_status launch_lsqr_finish(const LsqrJob& j, hipStream_t s) {
+  if (j.count == 0) return SNS_OK;
+  SNS_LAUNCH("lsqr_final", k_lsqr_xv, dim3(grid_for(j.ngemv)), dim3(kGemvThreads),
+             (size_t)j.maxn * sizeof(double), s, j.all, j.mgemv, 1);
+  SNS_LAUNCH("lsqr_report", k_lsqr_report, dim3(grid_for((uint32_t)j.count)), dim3(64), 0, s,
+             j.all, j.mone);
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
+}
+
+sns_status launch_lsqr_active(const LsqrJob& j, int* out, hipStream_t s) {
+  SNS_LAUNCH("lsqr_active", k_lsqr_active, dim3(1), dim3(256), 0, s, j.all, j.count, out);
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
+}
+
 namespace {
 
 // Host-side view of the device stop state, copied after every LSQR step into
@@ -585,46 +770,23 @@ PollRing& poll_ring() {
 
 }  // namespace
 
-sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan& p,
-                             const LsqrBufs& l, const QrBufs& q, int d, int max_iters,
-                             double rtol, double* x, sns_info* info_dev, hipStream_t s) {
-  const int n = (int)A.n;
-  if (n > 2048) return SNS_ERR_SHAPE;
-  const size_t es = A.dtype == SNS_F64 ? 8 : 4;
-  if ((uintptr_t)A.values % 16 != 0 || (A.ld * es) % 16 != 0) return SNS_ERR_SHAPE;
-  const double sighat = 1.0 - sqrt((double)n / (double)d);
-  const double stop = rtol > 0.0 ? rtol * (sighat > 0.0 ? sighat : 1.0) : 0.0;
-  double* wpass = l.vecs;
-  double* v = l.vecs + n;
-  double* wd = l.vecs + 2 * n;
-  double* dy = l.vecs + 3 * n;
-  double* ybuf = l.vecs + 4 * n;
-  LsqrState* st = static_cast<LsqrState*>(l.state);
-  SNS_LAUNCH("lsqr_init", k_lsqr_init, dim3(1), dim3(256), 0, s, n, max_iters, stop, st, q.xw, wpass,
-             dy);
-  SNS_LAUNCH("tri_inv", k_tri_inv, dim3(n), dim3(kInvThreads), ((size_t)n + 4096) * sizeof(double),
-             s, n, q.R, q.invd, l.Xc, l.Xr);
-  const unsigned gemv_grid = (unsigned)((n + kGemvRows - 1) / kGemvRows);
-  const size_t lds_xtz = ((size_t)n + 16 + kGemvRows) * sizeof(double);
-  const size_t lds_xv = (size_t)n * sizeof(double);
-  // iteration 0 is the residual pass r0 = b - A x0 plus the start-up step
-  auto enqueue = [&](int it) {
-    const void* uin = it == 0 ? b : l.u;
-    if (A.dtype == SNS_F64) launch_pass_v<double, 2>(A, p, l, uin, s);
-    else launch_pass_v<float, 4>(A, p, l, uin, s);
-    SNS_LAUNCH("lsqr_reduce", k_lsqr_reduce, dim3((n + 63) / 64, kRedSplit), dim3(256), 0, s, n,
-               p.grid, st, l.zpart, l.npart, l.zred2, l.nred2);
-    SNS_LAUNCH("lsqr_xtz", k_lsqr_xtz, dim3(gemv_grid), dim3(kGemvThreads), lds_xtz, s, n, sighat,
-               l.Xc, l.zred2, l.nred2, st, nullptr, ybuf, l.ypart, v, wd, dy);
-    SNS_LAUNCH("lsqr_xv", k_lsqr_xv, dim3(gemv_grid), dim3(kGemvThreads), lds_xv, s, n, l.Xr, v,
-               static_cast<const double*>(nullptr), st, 1, wpass);
-  };
+// One problem: set-up, iterations, final update.  Iteration 0 is the
+// residual pass r0 = b - A x0 plus the start-up step.  With `adaptive`, the
+// host reads the device stop state back while at most two iterations are in
+// flight; otherwise all max_iters + 1 steps are enqueued and the ones after
+// the stop rule return at once.
+sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipStream_t s) {
+  sns_status e = launch_lsqr_setup(j, s);
+  if (e != SNS_OK) return e;
+  const LsqrState* st = j.state;
+  const double stop = j.stop;
+  const double sighat = j.sighat;
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   SNS_HIP_TRY(hipStreamIsCapturing(s, &cap));
   PollRing& ring = poll_ring();
-  if (cap != hipStreamCaptureStatusNone || stop == 0.0 || !ring.ok) {
-    // fixed launch sequence; iterations after the stop rule return at once
-    for (int it = 0; it <= max_iters; ++it) enqueue(it);
+  if (!adaptive || !st || cap != hipStreamCaptureStatusNone || stop == 0.0 || !ring.ok) {
+    for (int it = 0; it <= max_iters; ++it)
+      if ((e = launch_lsqr_iteration(j, s)) != SNS_OK) return e;
   } else {
     // Keep at most two iterations in flight.  Before running ahead of an
     // unread iteration, predict from the geometric decay of the stop ratio
@@ -649,9 +811,8 @@ sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan&
       known = it;
       return SNS_OK;
     };
-    enqueue(0);
-    sns_status e = post(0);
-    if (e != SNS_OK) return e;
+    if ((e = launch_lsqr_iteration(j, s)) != SNS_OK) return e;
+    if ((e = post(0)) != SNS_OK) return e;
     int next = 1;
     while (next <= max_iters) {
       if (known < next - 1) {
@@ -669,7 +830,7 @@ sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan&
         }
       }
       if (known == next - 1 && done) break;
-      enqueue(next);
+      if ((e = launch_lsqr_iteration(j, s)) != SNS_OK) return e;
       if ((e = post(next)) != SNS_OK) return e;
       ++next;
       if (known < next - 2) {
@@ -678,12 +839,7 @@ sns_status launch_sap_refine(const sns_matrix& A, const void* b, const LsqrPlan&
       }
     }
   }
-  // x = x0 + X dy
-  SNS_LAUNCH("lsqr_final", k_lsqr_xv, dim3(gemv_grid), dim3(kGemvThreads), lds_xv, s, n, l.Xr, dy,
-             static_cast<const double*>(q.xw), st, 0, x);
-  SNS_LAUNCH("lsqr_report", k_lsqr_report, dim3(1), dim3(1), 0, s, st, info_dev);
-  SNS_HIP_TRY(hipGetLastError());
-  return SNS_OK;
+  return launch_lsqr_finish(j, s);
 }
 
 }  // namespace sns

@@ -23,13 +23,23 @@ namespace {
 
 constexpr int kPanelThreads = 512;
 
-// M[j * d + i] = SA[i * ld + j] (j < n), M[n * d + i] = Sb[i], via 32x32 tiles.
+// M[j * d + i] = SA[i * ld + j] (j < n), M[n * d + i] = Sb[i], via 32x32 tiles
+// (a work item is one tile).  The first tile also clears the scalar flags.
 template <typename T>
-__global__ void k_qr_load(int64_t d, int64_t n, const T* __restrict__ SA, int64_t ld,
-                          const T* __restrict__ Sb, double* __restrict__ M) {
+__global__ void k_qr_load(const QrArgs* __restrict__ P, Map mp) {
   __shared__ double tile[32][33];
-  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
   const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  const QrArgs& a = P[pi];
+  const uint32_t loc = it - mp.off[pi];
+  const int64_t d = a.d, n = a.n, ld = a.ld_sa;
+  const T* __restrict__ SA = static_cast<const T*>(a.SA);
+  const T* __restrict__ Sb = static_cast<const T*>(a.Sb);
+  const uint32_t tiles_i = (uint32_t)((d + 31) / 32);
+  const int64_t i0 = (int64_t)(loc % tiles_i) * 32, j0 = (int64_t)(loc / tiles_i) * 32;
+  if (loc == 0 && ty == 0 && tx < 8) a.scal[tx] = 0.0;
   for (int r = ty; r < 32; r += 8) {
     const int64_t i = i0 + r, j = j0 + tx;
     double v = 0.0;
@@ -40,7 +50,7 @@ __global__ void k_qr_load(int64_t d, int64_t n, const T* __restrict__ SA, int64_
   __syncthreads();
   for (int c = ty; c < 32; c += 8) {
     const int64_t j = j0 + c, i = i0 + tx;
-    if (i < d && j <= n) M[j * d + i] = tile[tx][c];
+    if (i < d && j <= n) a.M[j * d + i] = tile[tx][c];
   }
 }
 
@@ -121,39 +131,45 @@ __device__ __forceinline__ void panel_steps(double (&P)[MAXR][NB], int t, int64_
   }
 }
 
-// Factor panel columns [j0, j0 + nbw) of M over rows [j0, d).  Thread t owns
-// rows j0 + t + 512 r, r < MAXR.  Writes R entries, Householder vectors
-// (below the diagonal), tau, and T (NB x NB, column-major, upper).
+// Factor panel columns [j0, j0 + nbw) of M over rows [j0, d), nbw =
+// min(NB, n - j0).  Thread t owns rows j0 + t + 512 r, r < MAXR.  Writes R
+// entries, Householder vectors (below the diagonal), tau, and T (NB x NB,
+// column-major, upper).  One work item per problem; problems with n <= j0
+// have nothing to do.
 template <int MAXR, int NB>
-__global__ __launch_bounds__(kPanelThreads) void k_qr_panel(int64_t d, int64_t j0, int nbw,
-                                                            double* __restrict__ M,
-                                                            double* __restrict__ tau,
-                                                            double* __restrict__ Tg,
-                                                            double* __restrict__ flags) {
+__global__ __launch_bounds__(kPanelThreads) void k_qr_panel(const QrArgs* __restrict__ P, Map mp,
+                                                            int64_t j0) {
   __shared__ double red[kPanelThreads * NB];
   __shared__ double tot[NB];
   __shared__ double piv[NB];
   __shared__ double Ts[NB * NB];
   const int t = threadIdx.x;
-  double P[MAXR][NB];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const QrArgs& a = P[map_find(mp, it)];
+  const int64_t d = a.d;
+  if (j0 >= a.n) return;
+  const int nbw = (int)((a.n - j0) < NB ? (a.n - j0) : NB);
+  double* __restrict__ M = a.M;
+  double Pn[MAXR][NB];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
 #pragma unroll
-    for (int c = 0; c < NB; ++c) P[r][c] = (i < d && c < nbw) ? M[(j0 + c) * d + i] : 0.0;
+    for (int c = 0; c < NB; ++c) Pn[r][c] = (i < d && c < nbw) ? M[(j0 + c) * d + i] : 0.0;
   }
   for (int e = t; e < NB * NB; e += kPanelThreads) Ts[e] = 0.0;
   __syncthreads();
-  panel_steps<MAXR, NB, 0>(P, t, j0, d, nbw, red, tot, piv, Ts, tau, flags);
+  panel_steps<MAXR, NB, 0>(Pn, t, j0, d, nbw, red, tot, piv, Ts, a.tau, a.scal);
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
     if (i < d)
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c < nbw) M[(j0 + c) * d + i] = P[r][c];
+        if (c < nbw) M[(j0 + c) * d + i] = Pn[r][c];
   }
-  for (int e = t; e < NB * NB; e += kPanelThreads) Tg[e] = Ts[e];
+  for (int e = t; e < NB * NB; e += kPanelThreads) a.T[e] = Ts[e];
 }
 
 // C <- (I - V T V^T)^T C = C - V (T^T (V^T C)) for the trailing columns
@@ -173,16 +189,29 @@ __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t 
   return i > ja ? M[ja * d + i] : (i == ja ? 1.0 : 0.0);
 }
 
+// One work item per CB trailing columns; a problem owns ceil(n / CB) items,
+// of which the first ceil(ntr / CB) have columns at step j0.
 template <int NB>
-__global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(int64_t d, int64_t n, int64_t j0,
-                                                               int nbw, double* __restrict__ M,
-                                                               const double* __restrict__ Tg) {
+__global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(const QrArgs* __restrict__ P,
+                                                               Map mp, int64_t j0) {
   constexpr int CB = kTrailCB, NT = kTrailThreads, NV = NB * CB;
   __shared__ double red[NV * NT];
   __shared__ double W[NV];
   __shared__ double Wt[NV];
   const int t = threadIdx.x;
-  const int64_t jc0 = j0 + nbw + (int64_t)blockIdx.x * CB;
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  const QrArgs& a = P[pi];
+  const uint32_t loc = it - mp.off[pi];
+  const int64_t d = a.d, n = a.n;
+  if (j0 >= n) return;
+  const int nbw = (int)((n - j0) < NB ? (n - j0) : NB);
+  const int64_t ntr = n + 1 - (j0 + nbw);
+  if ((int64_t)loc * CB >= ntr) return;
+  double* __restrict__ M = a.M;
+  const double* __restrict__ Tg = a.T;
+  const int64_t jc0 = j0 + nbw + (int64_t)loc * CB;
   int64_t jc[CB];
   bool ok[CB];
 #pragma unroll
@@ -196,21 +225,21 @@ __global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(int64_t d, int64_
   for (int64_t i = j0 + t; i < d; i += NT) {
     double v[NB], cv[CB];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) v[a] = v_entry<NB>(M, d, j0, a, nbw, i);
+    for (int q = 0; q < NB; ++q) v[q] = v_entry<NB>(M, d, j0, q, nbw, i);
 #pragma unroll
     for (int c = 0; c < CB; ++c) cv[c] = ok[c] ? M[jc[c] * d + i] : 0.0;
 #pragma unroll
-    for (int a = 0; a < NB; ++a)
+    for (int q = 0; q < NB; ++q)
 #pragma unroll
-      for (int c = 0; c < CB; ++c) acc[a * CB + c] = fma(v[a], cv[c], acc[a * CB + c]);
+      for (int c = 0; c < CB; ++c) acc[q * CB + c] = fma(v[q], cv[c], acc[q * CB + c]);
   }
   block_reduce_multi<NV, NT>(acc, red, W);
   // W' = T^T W with T upper triangular (column-major NB x NB)
   if (t < NV) {
-    const int a = t / CB, c = t % CB;
+    const int q = t / CB, c = t % CB;
     double s = 0.0;
-    for (int b2 = 0; b2 <= a && b2 < nbw; ++b2) s += Tg[a * NB + b2] * W[b2 * CB + c];
-    Wt[t] = a < nbw ? s : 0.0;
+    for (int b2 = 0; b2 <= q && b2 < nbw; ++b2) s += Tg[q * NB + b2] * W[b2 * CB + c];
+    Wt[t] = q < nbw ? s : 0.0;
   }
   __syncthreads();
   double wt[NV];
@@ -219,30 +248,24 @@ __global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(int64_t d, int64_
   for (int64_t i = j0 + t; i < d; i += NT) {
     double v[NB];
 #pragma unroll
-    for (int a = 0; a < NB; ++a) v[a] = v_entry<NB>(M, d, j0, a, nbw, i);
+    for (int q = 0; q < NB; ++q) v[q] = v_entry<NB>(M, d, j0, q, nbw, i);
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       if (!ok[c]) continue;
       double s = 0.0;
 #pragma unroll
-      for (int a = 0; a < NB; ++a) s = fma(v[a], wt[a * CB + c], s);
+      for (int q = 0; q < NB; ++q) s = fma(v[q], wt[q * CB + c], s);
       M[jc[c] * d + i] -= s;
     }
   }
 }
 
 // rho, R (column-major copy and optional row-major output), rank and
-// finiteness checks, and x0 = R^{-1} c.  One work-group.
-__global__ __launch_bounds__(1024) void k_qr_finish(int64_t d, int64_t n,
-                                                    const double* __restrict__ M,
-                                                    double* __restrict__ Rc,
-                                                    double* __restrict__ Rr,
-                                                    double* __restrict__ invd,
-                                                    double* __restrict__ Rout,
-                                                    double* __restrict__ x0,
-                                                    double* __restrict__ flags,
-                                                    sns_info* __restrict__ info) {
-  extern __shared__ double sh[];
+// finiteness checks, and x0 = R^{-1} c.  One work item (1024 threads) per
+// problem.
+__device__ __forceinline__ void qr_finish_item(const QrArgs& a, double* sh) {
+  const int64_t d = a.d, n = a.n;
+  const double* __restrict__ M = a.M;
   double* x = sh;            // n
   double* blk = sh + n;      // 64 x 64
   double* red = blk + 4096;  // 16
@@ -256,11 +279,11 @@ __global__ __launch_bounds__(1024) void k_qr_finish(int64_t d, int64_t n,
   for (int64_t e = t; e < n * n; e += nt) {
     const int64_t j = e / n, i = e % n;  // Rc[j * n + i] = R[i, j]
     const double v = i <= j ? M[j * d + i] : 0.0;
-    Rc[e] = v;
-    Rr[i * n + j] = v;
-    if (Rout) Rout[i * n + j] = v;
+    a.R[e] = v;
+    a.Rr[i * n + j] = v;
+    if (a.Rout) a.Rout[i * n + j] = v;
   }
-  for (int64_t i = t; i < n; i += nt) invd[i] = 1.0 / M[i * d + i];
+  for (int64_t i = t; i < n; i += nt) a.invd[i] = 1.0 / M[i * d + i];
   double mx = 0.0;
   bool bad = false;
   for (int64_t i = t; i < n; i += nt) {
@@ -274,39 +297,48 @@ __global__ __launch_bounds__(1024) void k_qr_finish(int64_t d, int64_t n,
   for (int64_t i = t; i < n; i += nt)
     if (fabs(M[i * d + i]) <= thr) small = 1.0;
   const double rankdef = block_max(small, red);
-  const double nonfin = block_max(bad ? 1.0 : 0.0, red) + flags[2] + (isfinite(rho) ? 0.0 : 1.0);
+  const double nonfin =
+      block_max(bad ? 1.0 : 0.0, red) + a.scal[2] + (isfinite(rho) ? 0.0 : 1.0);
   for (int64_t i = t; i < n; i += nt) x[i] = M[n * d + i];
   __syncthreads();
   __syncthreads();
-  trsv_lds<true, 1024>(Rc, n, (int)n, invd, x, blk);
-  for (int64_t i = t; i < n; i += nt) x0[i] = x[i];
+  trsv_lds<true, 1024>(a.R, n, (int)n, a.invd, x, blk);
+  for (int64_t i = t; i < n; i += nt) a.x0[i] = x[i];
   if (t == 0) {
-    flags[0] = rho;
-    flags[1] = rankdef;
-    info->status = nonfin > 0.0 ? SNS_ERR_NUMERICAL : (rankdef > 0.0 ? SNS_ERR_RANK_DEFICIENT : SNS_OK);
+    a.scal[0] = rho;
+    a.scal[1] = rankdef;
+    sns_info* info = a.info;
+    info->status =
+        nonfin > 0.0 ? SNS_ERR_NUMERICAL : (rankdef > 0.0 ? SNS_ERR_RANK_DEFICIENT : SNS_OK);
     info->iters = 0;
     info->rel_resid_est = 0.0;
     info->sketch_resid = rho;
   }
 }
 
-__global__ void k_zero(double* p, int64_t count) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < count;
-       t += (int64_t)gridDim.x * blockDim.x)
-    p[t] = 0.0;
+__global__ __launch_bounds__(1024) void k_qr_finish(const QrArgs* __restrict__ P, Map mp) {
+  extern __shared__ double sh[];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  qr_finish_item(P[map_find(mp, it)], sh);
+}
+
+int qr_cfg(int64_t d) {
+  if (d <= 512) return 0;
+  if (d <= 1024) return 1;
+  if (d <= 2048) return 2;
+  if (d <= 4096) return 3;
+  return 4;
 }
 
 template <int MAXR, int NB>
-void run_panels(int64_t d, int64_t n, const QrBufs& q, hipStream_t st) {
-  for (int64_t j0 = 0; j0 < n; j0 += NB) {
-    const int nbw = (int)((n - j0) < NB ? (n - j0) : NB);
-    SNS_LAUNCH("qr_panel", (k_qr_panel<MAXR, NB>), dim3(1), dim3(kPanelThreads), 0, st, d, j0, nbw,
-                       q.M, q.tau, q.T, q.scal);
-    const int64_t ntr = n + 1 - (j0 + nbw);
-    if (ntr > 0)
-      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB>), dim3((unsigned)((ntr + kTrailCB - 1) / kTrailCB)),
-                 dim3(kTrailThreads), 0, st,
-                         d, n, j0, nbw, q.M, q.T);
+void run_panels(const QrJob::Cls& c, hipStream_t st) {
+  for (int64_t j0 = 0; j0 < c.maxn; j0 += NB) {
+    SNS_LAUNCH("qr_panel", (k_qr_panel<MAXR, NB>), dim3(grid_for((uint32_t)c.count)),
+               dim3(kPanelThreads), 0, st, c.args, c.mone, j0);
+    if (c.ntrail)
+      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB>), dim3(grid_for(c.ntrail)), dim3(kTrailThreads),
+                 0, st, c.args, c.mtrail, j0);
   }
 }
 
@@ -330,27 +362,86 @@ void carve_qr(Carve& c, int64_t d, int64_t n, QrBufs& q) {
   q.scal = c.take<double>(8);
 }
 
-sns_status launch_qr_solve(int64_t d, int64_t n, sns_dtype dt, const void* SA, int64_t ld_sa,
-                           const void* Sb, const QrBufs& q, double* x0, double* Rout,
-                           sns_info* info_dev, hipStream_t st) {
-  if (d > 8192 || n > 4096) return SNS_ERR_SHAPE;
-  SNS_LAUNCH("zero", k_zero, dim3(1), dim3(64), 0, st, q.scal, (int64_t)8);
-  const dim3 lg((unsigned)((d + 31) / 32), (unsigned)((n + 1 + 31) / 32));
-  if (dt == SNS_F64)
-    SNS_LAUNCH("qr_load", k_qr_load<double>, lg, dim3(32, 8), 0, st, d, n,
-                       static_cast<const double*>(SA), ld_sa, static_cast<const double*>(Sb), q.M);
+QrArgs qr_args(int64_t d, int64_t n, const void* SA, int64_t ld_sa, const void* Sb,
+               const QrBufs& q, double* x0, double* Rout, sns_info* info) {
+  QrArgs a;
+  a.d = d;
+  a.n = n;
+  a.ld_sa = ld_sa;
+  a.SA = SA;
+  a.Sb = Sb;
+  a.M = q.M;
+  a.T = q.T;
+  a.tau = q.tau;
+  a.R = q.R;
+  a.Rr = q.Rr;
+  a.invd = q.invd;
+  a.x0 = x0;
+  a.Rout = Rout;
+  a.scal = q.scal;
+  a.info = info;
+  return a;
+}
+
+QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
+  QrJob j;
+  j.f64 = f64;
+  j.count = (int)a.size();
+  if (a.empty()) return j;
+  std::vector<uint32_t> load, one;
+  for (const QrArgs& x : a) {
+    load.push_back((uint32_t)(((x.d + 31) / 32) * ((x.n + 1 + 31) / 32)));
+    one.push_back(1u);
+    j.maxn = x.n > j.maxn ? x.n : j.maxn;
+  }
+  j.all = t.add(a.data(), a.size());
+  j.mload = t.map(load, &j.nload);
+  uint32_t tmp = 0;
+  j.mone = t.map(one, &tmp);
+  for (int cfg = 0; cfg < 5; ++cfg) {
+    std::vector<QrArgs> sub;
+    std::vector<uint32_t> cone, ctr;
+    int64_t maxn = 0;
+    for (const QrArgs& x : a) {
+      if (qr_cfg(x.d) != cfg) continue;
+      sub.push_back(x);
+      cone.push_back(1u);
+      ctr.push_back((uint32_t)((x.n + kTrailCB - 1) / kTrailCB));
+      maxn = x.n > maxn ? x.n : maxn;
+    }
+    if (sub.empty()) continue;
+    QrJob::Cls c;
+    c.cfg = cfg;
+    c.args = t.add(sub.data(), sub.size());
+    c.mone = t.map(cone, &tmp);
+    c.mtrail = t.map(ctr, &c.ntrail);
+    c.count = (int)sub.size();
+    c.maxn = maxn;
+    j.cls.push_back(c);
+  }
+  return j;
+}
+
+sns_status launch_qr_job(const QrJob& j, hipStream_t st) {
+  if (j.count == 0) return SNS_OK;
+  if (j.f64)
+    SNS_LAUNCH("qr_load", k_qr_load<double>, dim3(grid_for(j.nload)), dim3(32, 8), 0, st, j.all,
+               j.mload);
   else
-    SNS_LAUNCH("qr_load", k_qr_load<float>, lg, dim3(32, 8), 0, st, d, n,
-                       static_cast<const float*>(SA), ld_sa, static_cast<const float*>(Sb), q.M);
-  if (d <= 512) run_panels<1, 16>(d, n, q, st);
-  else if (d <= 1024) run_panels<2, 16>(d, n, q, st);
-  else if (d <= 2048) run_panels<4, 16>(d, n, q, st);
-  else if (d <= 4096) run_panels<8, 8>(d, n, q, st);
-  else run_panels<16, 4>(d, n, q, st);
-  const size_t lds = ((size_t)n + 4096 + 16) * sizeof(double);
-  SNS_LAUNCH("qr_finish", k_qr_finish, dim3(1), dim3(1024), lds, st, d, n, q.M, q.R, q.Rr, q.invd,
-             Rout, x0, q.scal,
-                     info_dev);
+    SNS_LAUNCH("qr_load", k_qr_load<float>, dim3(grid_for(j.nload)), dim3(32, 8), 0, st, j.all,
+               j.mload);
+  for (const QrJob::Cls& c : j.cls) {
+    switch (c.cfg) {
+      case 0: run_panels<1, 16>(c, st); break;
+      case 1: run_panels<2, 16>(c, st); break;
+      case 2: run_panels<4, 16>(c, st); break;
+      case 3: run_panels<8, 8>(c, st); break;
+      default: run_panels<16, 4>(c, st); break;
+    }
+  }
+  const size_t lds = ((size_t)j.maxn + 4096 + 16) * sizeof(double);
+  SNS_LAUNCH("qr_finish", k_qr_finish, dim3(grid_for((uint32_t)j.count)), dim3(1024), lds, st,
+             j.all, j.mone);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }
