@@ -186,6 +186,38 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
                      const sns_solve_opts* opts, void* workspace, size_t ws_bytes,
                      sns_info* info, void* stream);
 
+/* One problem of a batch (sns_lstsq_batched). */
+typedef struct {
+  sns_sketch sketch;    /* CountSketch (SNS_SKETCH_COUNT) */
+  sns_matrix A;         /* dense row-major */
+  const void* b;        /* device, m entries of A's dtype */
+  double* x;            /* device fp64[n], the answer */
+  sns_solve_opts opts;  /* as for sns_lstsq */
+} sns_problem;
+
+/* Workspace bytes sns_lstsq_batched needs for these problems. */
+sns_status sns_lstsq_batched_workspace_size(const sns_problem* probs, int count, size_t* bytes);
+
+/* Solve `count` independent least-squares problems of uneven shapes together
+ * (Secs. 1.2, 1.3, 2.1 per problem): every kernel of the sketch, the QR and
+ * the refinement runs once for the whole batch, each work-group taking a
+ * piece of one problem.  Each problem's arithmetic is the one sns_lstsq does
+ * for it alone, so x and info are bit-identical to a solo sns_lstsq call.
+ * The refinement iterations of all problems advance together; a problem that
+ * met its stop rule skips the remaining iterations.  With use_graph != 0 a
+ * chunk of refinement iterations is captured once into a HIP graph and
+ * replayed until every problem has stopped.
+ * probs: HOST array of count problems, all of the same dtype, CountSketch,
+ * dense A (same limits as sns_lstsq).  infos: HOST array of count sns_info
+ * (pinned memory recommended) or NULL, written on the stream.  The call
+ * returns after the last refinement chunk has been enqueued (it waits on the
+ * stream between chunks to read the number of problems still running).
+ * Errors: as sns_lstsq for any problem; SNS_ERR_DTYPE if dtypes differ or a
+ * problem is not a dense CountSketch problem; SNS_ERR_INVALID_ARG if count <
+ * 1 or probs is NULL. */
+sns_status sns_lstsq_batched(const sns_problem* probs, int count, void* workspace,
+                             size_t ws_bytes, sns_info* infos, int use_graph, void* stream);
+
 /* Kernel timing (tracing support).  While enabled, every kernel the library
  * launches is bracketed by two HIP events on its stream; sns_timing_summary
  * waits for the recorded launches and writes one line per kernel name,

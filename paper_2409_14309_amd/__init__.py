@@ -7,12 +7,13 @@ Names follow the C ABI of include/sns.h.  Convenience wrappers (`sketch`,
 from __future__ import annotations
 
 from ._binding import (SNS_CSR, SNS_DENSE_ROWMAJOR, SNS_F32, SNS_F64, SNS_SKETCH_COUNT,  # noqa: F401
-                       SNS_SKETCH_GAUSSIAN, Info, Matrix, Sketch, SnsError, SolveOpts, csr, dense,
-                       exported_symbols, load, opts, sketch_desc, sns_gaussian_table, sns_hash,
-                       sns_lstsq, sns_lstsq_workspace_size, sns_qr_solve,
-                       sns_qr_solve_workspace_size, sns_sketch_apply, sns_sketch_workspace_size,
-                       sns_status_string, sns_timing_enable, sns_timing_reset,
-                       sns_timing_summary, sns_version)
+                       SNS_SKETCH_GAUSSIAN, Info, Matrix, Problem, Sketch, SnsError, SolveOpts,
+                       csr, dense, exported_symbols, load, opts, problem, sketch_desc,
+                       sns_gaussian_table, sns_hash, sns_lstsq, sns_lstsq_batched,
+                       sns_lstsq_batched_workspace_size, sns_lstsq_workspace_size,
+                       sns_qr_solve, sns_qr_solve_workspace_size, sns_sketch_apply,
+                       sns_sketch_workspace_size, sns_status_string, sns_timing_enable,
+                       sns_timing_reset, sns_timing_summary, sns_version)
 
 
 class CsrMatrix:
@@ -63,3 +64,20 @@ def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine: bool
     sns_lstsq(sk, M, b, x, o, ws, info, stream)
     (stream or torch.cuda.current_stream()).synchronize()
     return x, info
+
+
+def lstsq_batched(As, bs, ds, seeds, refine: bool = True, max_iters: int = 100, rtol: float = 1e-6,
+                  use_graph: bool = True, stream=None):
+    """Solve several dense problems in one batch; returns ([x], [Info])."""
+    import torch
+    probs, xs = [], []
+    for A, b, d, seed in zip(As, bs, ds, seeds):
+        x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+        o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0)
+        probs.append(problem(sketch_desc("count", d, seed), dense(A), b, x, o))
+        xs.append(x)
+    ws = _workspace(sns_lstsq_batched_workspace_size(probs), As[0].device)
+    infos = (Info * len(probs))()
+    sns_lstsq_batched(probs, ws, infos, use_graph, stream)
+    (stream or torch.cuda.current_stream()).synchronize()
+    return xs, list(infos)

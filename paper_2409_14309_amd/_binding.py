@@ -48,6 +48,11 @@ class Info(C.Structure):
                 ("sketch_resid", C.c_double)]
 
 
+class Problem(C.Structure):
+    _fields_ = [("sketch", Sketch), ("A", Matrix), ("b", C.c_void_p), ("x", C.c_void_p),
+                ("opts", SolveOpts)]
+
+
 _lib = None
 
 _SIGS = {
@@ -70,6 +75,10 @@ _SIGS = {
     "sns_lstsq": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix), C.c_void_p, C.c_void_p,
                             C.POINTER(SolveOpts), C.c_void_p, C.c_size_t, C.POINTER(Info),
                             C.c_void_p]),
+    "sns_lstsq_batched_workspace_size": (C.c_int, [C.POINTER(Problem), C.c_int,
+                                                   C.POINTER(C.c_size_t)]),
+    "sns_lstsq_batched": (C.c_int, [C.POINTER(Problem), C.c_int, C.c_void_p, C.c_size_t,
+                                    C.POINTER(Info), C.c_int, C.c_void_p]),
     "sns_timing_enable": (None, [C.c_int]),
     "sns_timing_reset": (None, []),
     "sns_timing_summary": (C.c_int, [C.c_char_p, C.c_size_t]),
@@ -212,6 +221,27 @@ def sns_lstsq(sk: Sketch, A: Matrix, b, x, opt: SolveOpts, workspace, info: Info
                             _ptr(workspace), workspace.numel() * workspace.element_size(),
                             C.byref(info) if info is not None else None, _stream(stream)),
            "sns_lstsq")
+
+
+def problem(sk: Sketch, A: Matrix, b, x, opt: SolveOpts) -> Problem:
+    return Problem(sk, A, b.data_ptr(), x.data_ptr(), opt)
+
+
+def sns_lstsq_batched_workspace_size(probs) -> int:
+    arr = (Problem * len(probs))(*probs)
+    n = C.c_size_t(0)
+    _check(load().sns_lstsq_batched_workspace_size(arr, len(probs), C.byref(n)),
+           "sns_lstsq_batched_workspace_size")
+    return n.value
+
+
+def sns_lstsq_batched(probs, workspace, infos=None, use_graph: bool = True, stream=None):
+    """infos: a ctypes array of Info (len(probs)) or None."""
+    arr = (Problem * len(probs))(*probs)
+    _check(load().sns_lstsq_batched(arr, len(probs), _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(), infos,
+                                    1 if use_graph else 0, _stream(stream)),
+           "sns_lstsq_batched")
 
 
 # ------------------------------------------------------------- timing ----

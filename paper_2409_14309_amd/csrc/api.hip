@@ -167,6 +167,156 @@ sns_solve_opts default_opts() {
   return o;
 }
 
+// Checks of sns_lstsq beyond those of the sketch.
+sns_status check_solve(const sns_sketch& sk, const sns_matrix& A, const sns_solve_opts& o) {
+  if (o.refine && (o.max_iters < 0 || !(o.rtol >= 0.0))) return SNS_ERR_INVALID_ARG;
+  if (A.n > 4096 || sk.d > kMaxQrD) return SNS_ERR_SHAPE;
+  if (o.refine && A.n > 2048) return SNS_ERR_SHAPE;
+  if (o.refine && A.layout == SNS_CSR) return SNS_ERR_DTYPE;  // refinement streams dense rows
+  if (o.refine && (((uintptr_t)A.values % 16) != 0 || (A.ld * elem(A)) % 16 != 0))
+    return SNS_ERR_SHAPE;
+  return SNS_OK;
+}
+
+// ------------------------------------------------------------- batches ----
+// Per-problem buffers of a batch; the argument table and the shared scalars
+// follow them.
+struct BatchWs {
+  std::vector<LstsqWs> w;
+  sns_info* infos = nullptr;  // count entries, contiguous
+  int* active = nullptr;      // problems still refining
+  char* args = nullptr;
+};
+
+void build_batch_jobs(ArgTable& t, Jobs& J, const sns_problem* P, int count, const BatchWs& B,
+                      bool real) {
+  std::vector<SortArgs> sa;
+  std::vector<GatherProb> ga;
+  std::vector<QrArgs> qa;
+  std::vector<LsqrProb> la;
+  for (int i = 0; i < count; ++i) {
+    const sns_problem& q = P[i];
+    const LstsqWs& w = B.w[i];
+    const void* b = real ? q.b : nullptr;
+    sa.push_back(sort_args(w.sw.sp, q.sketch.seed, b, w.sw.sb));
+    GatherProb g;
+    g.plan = w.sw.gp;
+    g.args = gather_args(w.sw.gp, q.A, (uint32_t)q.sketch.d, w.sw.sb, true, w.SA, w.Sb, w.sw.part);
+    g.dtype = q.A.dtype;
+    ga.push_back(g);
+    qa.push_back(qr_args(q.sketch.d, q.A.n, w.SA, q.A.n, w.Sb, w.q, w.q.xw, nullptr, B.infos + i));
+    if (q.opts.refine) {
+      LsqrProb lp;
+      lp.plan = w.lp;
+      lp.args = lsqr_args(q.A, b, w.lp, w.l, w.q, (int)q.sketch.d, q.opts.max_iters, q.opts.rtol,
+                          real ? q.x : nullptr, B.infos + i);
+      la.push_back(lp);
+    }
+  }
+  const bool f64 = P[0].A.dtype == SNS_F64;
+  J.sort = build_sort_job(t, sa, f64);
+  J.gather = build_gather_job(t, ga);
+  J.qr = build_qr_job(t, qa, f64);
+  J.lsqr = build_lsqr_job(t, la, f64);
+}
+
+void carve_batch(Carve& c, const sns_problem* P, int count, BatchWs& B) {
+  B.w.assign(count, LstsqWs{});
+  B.infos = c.take<sns_info>((size_t)count);
+  B.active = c.take<int>(1);
+  for (int i = 0; i < count; ++i) carve_lstsq_bufs(c, P[i].sketch, P[i].A, P[i].opts, B.w[i]);
+  ArgTable t0(nullptr);
+  Jobs J0;
+  build_batch_jobs(t0, J0, P, count, B, false);
+  B.args = c.take<char>(t0.bytes());
+}
+
+sns_status check_batch(const sns_problem* P, int count) {
+  if (!P || count < 1) return SNS_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i) {
+    const sns_problem& q = P[i];
+    sns_status s = check_matrix(&q.A);
+    if (s != SNS_OK) return s;
+    if ((s = check_sketch(&q.sketch, &q.A)) != SNS_OK) return s;
+    if (q.sketch.kind != SNS_SKETCH_COUNT || q.A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+    if (q.A.dtype != P[0].A.dtype) return SNS_ERR_DTYPE;
+    if ((s = check_solve(q.sketch, q.A, q.opts)) != SNS_OK) return s;
+  }
+  return SNS_OK;
+}
+
+// A private stream for capturing graphs (capture is not possible on the
+// legacy default stream a caller may pass).
+hipStream_t capture_stream() {
+  thread_local hipStream_t s = nullptr;
+  if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  return s;
+}
+
+struct PinnedInt {
+  int* p = nullptr;
+  hipEvent_t ev = nullptr;
+  PinnedInt() {
+    if (hipHostMalloc((void**)&p, sizeof(int), hipHostMallocDefault) != hipSuccess) p = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+  }
+};
+
+PinnedInt& pinned_int() {
+  thread_local PinnedInt r;
+  return r;
+}
+
+constexpr int kChunkIters = 4;  // refinement iterations per chunk
+
+// Refinement of a batch: setup, chunks of iterations until no problem is
+// left running (read back between chunks), final update and report.
+sns_status run_batch_lsqr(const LsqrJob& j, int max_iters, int* active_dev, bool use_graph,
+                          hipStream_t st) {
+  if (j.count == 0) return SNS_OK;
+  sns_status s = launch_lsqr_setup(j, st);
+  if (s != SNS_OK) return s;
+  PinnedInt& pi = pinned_int();
+  if (!pi.p || !pi.ev) return SNS_ERR_HIP;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  if (use_graph) {
+    hipStream_t cs = capture_stream();
+    if (!cs) return SNS_ERR_HIP;
+    SNS_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kChunkIters && s == SNS_OK; ++k) s = launch_lsqr_iteration(j, cs);
+    if (s == SNS_OK) s = launch_lsqr_active(j, active_dev, cs);
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (s != SNS_OK) return s;
+    SNS_HIP_TRY(e);
+    if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return SNS_ERR_HIP;
+    }
+  }
+  // iteration 0 is the residual pass; iterations past a problem's own
+  // max_iters or stop rule return at once
+  for (int done = 0; done <= max_iters; done += kChunkIters) {
+    if (use_graph) {
+      if (hipGraphLaunch(exec, st) != hipSuccess) { s = SNS_ERR_HIP; break; }
+    } else {
+      for (int k = 0; k < kChunkIters && s == SNS_OK; ++k) s = launch_lsqr_iteration(j, st);
+      if (s == SNS_OK) s = launch_lsqr_active(j, active_dev, st);
+      if (s != SNS_OK) break;
+    }
+    if (hipMemcpyAsync(pi.p, active_dev, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipEventRecord(pi.ev, st) != hipSuccess || hipEventSynchronize(pi.ev) != hipSuccess) {
+      s = SNS_ERR_HIP;
+      break;
+    }
+    if (*pi.p == 0) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (s != SNS_OK) return s;
+  return launch_lsqr_finish(j, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -320,12 +470,7 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   if ((s = check_sketch(sk, A)) != SNS_OK) return s;
   if (!b || !x || !workspace) return SNS_ERR_INVALID_ARG;
   const sns_solve_opts o = opts ? *opts : default_opts();
-  if (o.refine && (o.max_iters < 0 || !(o.rtol >= 0.0))) return SNS_ERR_INVALID_ARG;
-  if (A->n > 4096 || sk->d > kMaxQrD) return SNS_ERR_SHAPE;
-  if (o.refine && A->n > 2048) return SNS_ERR_SHAPE;
-  if (o.refine && A->layout == SNS_CSR) return SNS_ERR_DTYPE;  // refinement streams dense rows
-  if (o.refine && (((uintptr_t)A->values % 16) != 0 || (A->ld * elem(*A)) % 16 != 0))
-    return SNS_ERR_SHAPE;
+  if ((s = check_solve(*sk, *A, o)) != SNS_OK) return s;
   Carve c(workspace, ws_bytes);
   LstsqWs w;
   carve_lstsq(c, *sk, *A, o, w);
@@ -350,6 +495,49 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
     SNS_HIP_TRY(hipMemcpyAsync(x, w.q.xw, sizeof(double) * A->n, hipMemcpyDeviceToDevice, st));
   }
   if (info) SNS_HIP_TRY(hipMemcpyAsync(info, w.info, sizeof(sns_info), hipMemcpyDeviceToHost, st));
+  return SNS_OK;
+}
+
+sns_status sns_lstsq_batched_workspace_size(const sns_problem* probs, int count, size_t* bytes) {
+  sns_status s = check_batch(probs, count);
+  if (s != SNS_OK) return s;
+  if (!bytes) return SNS_ERR_INVALID_ARG;
+  Carve c(nullptr, 0);
+  BatchWs B;
+  carve_batch(c, probs, count, B);
+  *bytes = c.off;
+  return SNS_OK;
+}
+
+sns_status sns_lstsq_batched(const sns_problem* probs, int count, void* workspace,
+                             size_t ws_bytes, sns_info* infos, int use_graph, void* stream) {
+  sns_status s = check_batch(probs, count);
+  if (s != SNS_OK) return s;
+  if (!workspace) return SNS_ERR_INVALID_ARG;
+  for (int i = 0; i < count; ++i)
+    if (!probs[i].b || !probs[i].x) return SNS_ERR_INVALID_ARG;
+  Carve c(workspace, ws_bytes);
+  BatchWs B;
+  carve_batch(c, probs, count, B);
+  if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
+  hipStream_t st = (hipStream_t)stream;
+  ArgTable t(B.args);
+  Jobs J;
+  build_batch_jobs(t, J, probs, count, B, true);
+  if ((s = t.upload(st)) != SNS_OK) return s;
+  if ((s = run_sketch_jobs(J, st)) != SNS_OK) return s;
+  if ((s = launch_qr_job(J.qr, st)) != SNS_OK) return s;
+  int max_iters = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!probs[i].opts.refine)
+      SNS_HIP_TRY(hipMemcpyAsync(probs[i].x, B.w[i].q.xw, sizeof(double) * probs[i].A.n,
+                                 hipMemcpyDeviceToDevice, st));
+    else if (probs[i].opts.max_iters > max_iters)
+      max_iters = probs[i].opts.max_iters;
+  }
+  if ((s = run_batch_lsqr(J.lsqr, max_iters, B.active, use_graph != 0, st)) != SNS_OK) return s;
+  if (infos)
+    SNS_HIP_TRY(hipMemcpyAsync(infos, B.infos, sizeof(sns_info) * count, hipMemcpyDeviceToHost, st));
   return SNS_OK;
 }
 

@@ -90,6 +90,9 @@ void timing_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> g(r.mu);
   check_env(r);
   if (!r.on) return;
+  // launches being captured into a graph are not timed
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
   t_pending.name = name;
   t_pending.a = take_event(r);
   t_pending.b = take_event(r);
