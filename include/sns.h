@@ -218,6 +218,65 @@ sns_status sns_lstsq_batched_workspace_size(const sns_problem* probs, int count,
 sns_status sns_lstsq_batched(const sns_problem* probs, int count, void* workspace,
                              size_t ws_bytes, sns_info* infos, int use_graph, void* stream);
 
+/* ------------------------------------------------------------- serving --
+ * A server solves submitted problems with continuous batching.  A scheduler
+ * thread owns a HIP stream and works in rounds: it admits waiting requests
+ * in arrival order while a slot is free and the request's workspace fits in
+ * the pool (admission by device-memory footprint), sets the admitted ones up
+ * together (sketch, QR, X = R^{-1}; one batched launch per kernel), advances
+ * every admitted request by a chunk of refinement iterations in one batched
+ * launch per kernel, and retires the requests whose stop rule has fired.
+ * Requests that arrive while others run join at the next round, so their
+ * work shares launches with the running ones.  Each request's arithmetic is
+ * the one sns_lstsq does for it alone: x and info are bit-identical to a
+ * solo call whatever else is in flight. */
+typedef struct sns_server sns_server;
+
+typedef struct {
+  void* pool;          /* device memory for request workspaces (caller-owned) */
+  size_t pool_bytes;
+  sns_dtype dtype;     /* element type of every request's A and b */
+  int max_slots;       /* requests admitted at once, 1..4096 */
+  int queue_capacity;  /* requests waiting for admission, >= 1 */
+  int chunk_iters;     /* refinement iterations per round, >= 1 */
+} sns_serve_config;
+
+typedef struct {
+  uint64_t submitted, completed;
+  double p50_ms, p99_ms, mean_ms;  /* latency from submit to result, completed requests */
+  double span_s;                   /* first submit to last completion */
+  size_t peak_pool_bytes;          /* most pool bytes in use at once */
+  int peak_slots;                  /* most requests admitted at once */
+  uint64_t rounds;                 /* scheduling rounds run */
+} sns_serve_stats;
+
+/* Create a server on the current device.  Errors: SNS_ERR_INVALID_ARG (NULL
+ * arguments or a field out of range), SNS_ERR_OUT_OF_MEMORY (pool too small
+ * for the server's own tables), SNS_ERR_HIP. */
+sns_status sns_serve_create(const sns_serve_config* cfg, sns_server** out);
+
+/* Queue one problem (same rules as sns_lstsq: dense CountSketch, A, b and x in
+ * device memory, written before the call; they must stay valid until the
+ * request completes).  *ticket identifies the request.  Errors: as sns_lstsq
+ * (checked now), SNS_ERR_DTYPE (dtype differs from the server's),
+ * SNS_ERR_OUT_OF_MEMORY (workspace larger than the pool), SNS_ERR_QUEUE_FULL. */
+sns_status sns_serve_submit(sns_server* srv, const sns_problem* req, uint64_t* ticket);
+
+/* SNS_OK and *out filled (host pointer, may be NULL) once the request has
+ * completed (x written); the ticket is then released.  SNS_ERR_NOT_READY while
+ * it runs; SNS_ERR_INVALID_ARG for an unknown ticket. */
+sns_status sns_serve_poll(sns_server* srv, uint64_t ticket, sns_info* out);
+
+/* As sns_serve_poll, but blocks until the request has completed. */
+sns_status sns_serve_wait(sns_server* srv, uint64_t ticket, sns_info* out);
+
+/* Counters and latency percentiles so far (host pointer). */
+sns_status sns_serve_stats_get(sns_server* srv, sns_serve_stats* out);
+
+/* Completes every submitted request, stops the scheduler and frees the
+ * server (not the pool). */
+sns_status sns_serve_destroy(sns_server* srv);
+
 /* Kernel timing (tracing support).  While enabled, every kernel the library
  * launches is bracketed by two HIP events on its stream; sns_timing_summary
  * waits for the recorded launches and writes one line per kernel name,

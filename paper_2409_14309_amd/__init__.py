@@ -7,6 +7,8 @@ Names follow the C ABI of include/sns.h.  Convenience wrappers (`sketch`,
 from __future__ import annotations
 
 from ._binding import (SNS_CSR, SNS_DENSE_ROWMAJOR, SNS_F32, SNS_F64, SNS_SKETCH_COUNT,  # noqa: F401
+                       ServeConfig, ServeStats, sns_serve_create, sns_serve_destroy,
+                       sns_serve_poll, sns_serve_stats_get, sns_serve_submit, sns_serve_wait,
                        SNS_SKETCH_GAUSSIAN, Info, Matrix, Problem, Sketch, SnsError, SolveOpts,
                        csr, dense, exported_symbols, load, opts, problem, sketch_desc,
                        sns_gaussian_table, sns_hash, sns_lstsq, sns_lstsq_batched,
@@ -81,3 +83,53 @@ def lstsq_batched(As, bs, ds, seeds, refine: bool = True, max_iters: int = 100, 
     sns_lstsq_batched(probs, ws, infos, use_graph, stream)
     (stream or torch.cuda.current_stream()).synchronize()
     return xs, list(infos)
+
+
+class Server:
+    """Continuous-batching solver service over a device memory pool.
+
+    submit() queues a dense CountSketch problem (device tensors A, b; the
+    answer goes to a new fp64 tensor) and returns a ticket; wait()/poll()
+    return (x, Info) once it has completed."""
+
+    def __init__(self, pool_bytes: int, dtype=None, max_slots: int = 64,
+                 queue_capacity: int = 65536, chunk_iters: int = 4, device=None):
+        import torch
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device or "cuda")
+        code = SNS_F64 if dtype == torch.float64 else SNS_F32
+        self.handle = sns_serve_create(self.pool, code, max_slots, queue_capacity, chunk_iters)
+        self._live = {}
+
+    def submit(self, A, b, d: int, seed: int, refine: bool = True, max_iters: int = 100,
+               rtol: float = 1e-6, x=None) -> int:
+        import torch
+        if x is None:
+            x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
+        o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0)
+        t = sns_serve_submit(self.handle, problem(sketch_desc("count", d, seed), dense(A), b, x, o))
+        self._live[t] = (A, b, x)  # keep the buffers alive while the request runs
+        return t
+
+    def poll(self, ticket: int):
+        info = sns_serve_poll(self.handle, ticket)
+        if info is None:
+            return None
+        return self._live.pop(ticket)[2], info
+
+    def wait(self, ticket: int):
+        info = sns_serve_wait(self.handle, ticket)
+        return self._live.pop(ticket)[2], info
+
+    def stats(self):
+        return sns_serve_stats_get(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            sns_serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -16,6 +16,7 @@ SNS_OK = 0
 STATUS_NAMES = ["SNS_OK", "SNS_ERR_INVALID_ARG", "SNS_ERR_SHAPE", "SNS_ERR_DTYPE",
                 "SNS_ERR_RANK_DEFICIENT", "SNS_ERR_NOT_CONVERGED", "SNS_ERR_NUMERICAL",
                 "SNS_ERR_OUT_OF_MEMORY", "SNS_ERR_QUEUE_FULL", "SNS_ERR_NOT_READY", "SNS_ERR_HIP"]
+SNS_ERR_QUEUE_FULL, SNS_ERR_NOT_READY = 8, 9
 SNS_F32, SNS_F64 = 0, 1
 SNS_DENSE_ROWMAJOR, SNS_CSR = 0, 1
 SNS_SKETCH_COUNT, SNS_SKETCH_GAUSSIAN = 0, 1
@@ -53,6 +54,17 @@ class Problem(C.Structure):
                 ("opts", SolveOpts)]
 
 
+class ServeConfig(C.Structure):
+    _fields_ = [("pool", C.c_void_p), ("pool_bytes", C.c_size_t), ("dtype", C.c_int),
+                ("max_slots", C.c_int), ("queue_capacity", C.c_int), ("chunk_iters", C.c_int)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("p50_ms", C.c_double),
+                ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("span_s", C.c_double),
+                ("peak_pool_bytes", C.c_size_t), ("peak_slots", C.c_int), ("rounds", C.c_uint64)]
+
+
 _lib = None
 
 _SIGS = {
@@ -79,6 +91,12 @@ _SIGS = {
                                                    C.POINTER(C.c_size_t)]),
     "sns_lstsq_batched": (C.c_int, [C.POINTER(Problem), C.c_int, C.c_void_p, C.c_size_t,
                                     C.POINTER(Info), C.c_int, C.c_void_p]),
+    "sns_serve_create": (C.c_int, [C.POINTER(ServeConfig), C.POINTER(C.c_void_p)]),
+    "sns_serve_submit": (C.c_int, [C.c_void_p, C.POINTER(Problem), C.POINTER(C.c_uint64)]),
+    "sns_serve_poll": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Info)]),
+    "sns_serve_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Info)]),
+    "sns_serve_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ServeStats)]),
+    "sns_serve_destroy": (C.c_int, [C.c_void_p]),
     "sns_timing_enable": (None, [C.c_int]),
     "sns_timing_reset": (None, []),
     "sns_timing_summary": (C.c_int, [C.c_char_p, C.c_size_t]),
@@ -242,6 +260,50 @@ def sns_lstsq_batched(probs, workspace, infos=None, use_graph: bool = True, stre
                                     workspace.numel() * workspace.element_size(), infos,
                                     1 if use_graph else 0, _stream(stream)),
            "sns_lstsq_batched")
+
+
+# ------------------------------------------------------------ serving ----
+
+def sns_serve_create(pool, dtype: int, max_slots: int = 64, queue_capacity: int = 65536,
+                     chunk_iters: int = 4):
+    """Server handle over the device tensor `pool` (kept alive by the caller)."""
+    cfg = ServeConfig(pool.data_ptr(), pool.numel() * pool.element_size(), dtype, max_slots,
+                      queue_capacity, chunk_iters)
+    h = C.c_void_p()
+    _check(load().sns_serve_create(C.byref(cfg), C.byref(h)), "sns_serve_create")
+    return h
+
+
+def sns_serve_submit(srv, prob: Problem) -> int:
+    t = C.c_uint64(0)
+    _check(load().sns_serve_submit(srv, C.byref(prob), C.byref(t)), "sns_serve_submit")
+    return t.value
+
+
+def sns_serve_poll(srv, ticket: int):
+    """Info once the request has completed, else None."""
+    info = Info()
+    st = load().sns_serve_poll(srv, ticket, C.byref(info))
+    if st == SNS_ERR_NOT_READY:
+        return None
+    _check(st, "sns_serve_poll")
+    return info
+
+
+def sns_serve_wait(srv, ticket: int) -> Info:
+    info = Info()
+    _check(load().sns_serve_wait(srv, ticket, C.byref(info)), "sns_serve_wait")
+    return info
+
+
+def sns_serve_stats_get(srv) -> ServeStats:
+    s = ServeStats()
+    _check(load().sns_serve_stats_get(srv, C.byref(s)), "sns_serve_stats_get")
+    return s
+
+
+def sns_serve_destroy(srv):
+    _check(load().sns_serve_destroy(srv), "sns_serve_destroy")
 
 
 # ------------------------------------------------------------- timing ----

@@ -336,6 +336,8 @@ sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipSt
 // Number of problems of the job that have not stopped, written to *out
 // (device int) on the stream.
 sns_status launch_lsqr_active(const LsqrJob& j, int* out, hipStream_t st);
+// out[p] (device ints) = 1 once problem p of the job has stopped.
+sns_status launch_lsqr_flags(const LsqrJob& j, int* out, hipStream_t st);
 
 // ------------------------------------------------------------- Gaussian ----
 const uint16_t* gauss_table_host();

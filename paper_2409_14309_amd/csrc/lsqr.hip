@@ -520,6 +520,12 @@ __global__ void k_lsqr_report(const LsqrArgs* __restrict__ P, Map mp) {
   if (info->status == SNS_OK) info->status = st->status;
 }
 
+// out[p] = 1 once problem p has stopped.
+__global__ void k_lsqr_flags(const LsqrArgs* __restrict__ P, int nprob, int* __restrict__ out) {
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nprob; p += gridDim.x * blockDim.x)
+    out[p] = P[p].st->done ? 1 : 0;
+}
+
 // Number of problems not yet stopped.
 __global__ void k_lsqr_active(const LsqrArgs* __restrict__ P, int nprob, int* __restrict__ out) {
   __shared__ int red[4];
@@ -740,6 +746,14 @@ sns_status launch_lsqr_finish(const LsqrJob& j, hipStream_t s) {
 
 sns_status launch_lsqr_active(const LsqrJob& j, int* out, hipStream_t s) {
   SNS_LAUNCH("lsqr_active", k_lsqr_active, dim3(1), dim3(256), 0, s, j.all, j.count, out);
+  SNS_HIP_TRY(hipGetLastError());
+  return SNS_OK;
+}
+
+sns_status launch_lsqr_flags(const LsqrJob& j, int* out, hipStream_t s) {
+  if (j.count == 0) return SNS_OK;
+  SNS_LAUNCH("lsqr_flags", k_lsqr_flags, dim3((j.count + 255) / 256), dim3(256), 0, s, j.all,
+             j.count, out);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }
