@@ -83,15 +83,175 @@ def cpu_baseline(A, b, d, rtol, rows, full_m, kind):
             "seconds_sample": dt}
 
 
+SERVE_WORKLOAD = "serve_mix_10000"
+
+
+def serve_main(args):
+    """Serving mix: Poisson arrivals, m log-uniform in [2^12, 2^20], n in
+    {16, ..., 256}, d = 4 n, FP32, refined to the stop rule; open loop at the
+    arrival rate and saturated (all queued at once) through the
+    continuous-batching server, against one-problem-at-a-time GPU solves."""
+    import numpy as np
+    import torch
+
+    import paper_2409_14309_amd as sns
+    import workloads
+
+    sns.load()
+    rows = 1 << 20
+    reqs = workloads.serving_requests(args.requests, args.rate, seed=1004)
+    log(f"generating the device pools ({rows} rows per n) ...")
+    pool = workloads.serving_pool(rows, seed=1004)
+    torch.cuda.synchronize()
+
+    def window(r, P):
+        o = workloads.request_window(r, rows)
+        return P[r["n"]]["A"][o:o + r["m"]], P[r["n"]]["b"][o:o + r["m"]]
+
+    pool_bytes = args.slots * (40 << 20)
+
+    def serve(open_loop, subset):
+        srv = sns.Server(pool_bytes, max_slots=args.slots, chunk_iters=args.chunk)
+        tickets = []
+        t0 = time.perf_counter()
+        for r in subset:
+            if open_loop:
+                delay = t0 + r["t"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            A, b = window(r, pool)
+            tickets.append((r, srv.submit(A, b, r["d"], 42, max_iters=args.max_iters,
+                                          rtol=args.rtol)))
+        res = [(r, *srv.wait(t)) for r, t in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return res, st, wall
+
+    serve(False, reqs[:64])  # warm-up
+    log(f"open loop: {len(reqs)} requests at {args.rate}/s ...")
+    res_o, st_o, wall_o = serve(True, reqs)
+    log(f"  {st_o.completed} done in {wall_o:.2f}s; p50 {st_o.p50_ms:.2f} ms p99 {st_o.p99_ms:.2f} ms")
+    log("saturation: all requests queued at once ...")
+    res_s, st_s, wall_s = serve(False, reqs)
+    log(f"  {st_s.completed} done in {wall_s:.2f}s ({st_s.completed / wall_s:.1f} solves/s)")
+
+    # algorithmic HBM bytes of the saturated run: sketch pass + (iters + 1) LSQR passes
+    tot = 0.0
+    for r, x, info in res_s:
+        m, n = r["m"], r["n"]
+        tot += 4.0 * m * (n + 1) + (info.iters + 1) * (4.0 * m * n + 8.0 * m)
+    bad = [int(info.status) for _, _, info in res_s if info.status != 0]
+
+    # one problem at a time on the GPU, same stop rule: FP64 (the plain
+    # per-problem form) and FP32
+    nb = min(args.baseline_requests, len(reqs))
+    base = {}
+    for tag, fp64 in (("per_problem_fp32", False), ("per_problem_fp64", True)):
+        P = pool if not fp64 else workloads.serving_pool(rows, seed=1004, fp64=True)
+        torch.cuda.synchronize()
+        for r in reqs[:4]:
+            A, b = window(r, P)
+            sns.lstsq(A, b, "count", r["d"], 42, refine=True, max_iters=args.max_iters, rtol=args.rtol)
+        t0 = time.perf_counter()
+        lat = []
+        for r in reqs[:nb]:
+            t1 = time.perf_counter()
+            A, b = window(r, P)
+            sns.lstsq(A, b, "count", r["d"], 42, refine=True, max_iters=args.max_iters, rtol=args.rtol)
+            lat.append(1000.0 * (time.perf_counter() - t1))
+        dt = time.perf_counter() - t0
+        base[tag] = {"solves_per_s": round(nb / dt, 2), "requests": nb,
+                     "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        log(f"  {tag}: {nb / dt:.1f} solves/s")
+        if fp64:
+            del P
+            torch.cuda.empty_cache()
+
+    # residual error of a sample of the served answers against FP64 lstsq
+    from oracle import metrics as OM
+    worst = 0.0
+    checked = 0
+    for r, x, info in res_s:
+        if r["m"] > (1 << 15) or checked >= 12:
+            continue
+        A, b = window(r, pool)
+        An, bn = A.cpu().numpy(), b.cpu().numpy()
+        met = OM.metrics(An, bn, x.cpu().numpy(), OM.lstsq_exact(An, bn))
+        worst = max(worst, met["RE"])
+        checked += 1
+
+    cpu = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_info
+
+        from oracle import solve as OSV
+        k = min(args.cpu_requests, len(reqs))
+        log(f"timing the CPU oracle on the first {k} requests ...")
+        t0 = time.perf_counter()
+        for r in reqs[:k]:
+            A, b = window(r, pool)
+            OSV.sap_sas(A.cpu().numpy(), b.cpu().numpy(), "count", 42, r["d"], args.max_iters,
+                        rtol=args.rtol)
+        dt = time.perf_counter() - t0
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        cpu = {"value": round(k / dt, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {k} requests of the stream solved one after another in {dt:.1f}s"}
+
+    sat = st_s.completed / wall_s
+    out = {
+        "metric": "LS solves/s + p50/p99 latency at rel-residual 1e-6, serving mix",
+        "value": round(sat, 2),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 64,
+        "ms_per_step": round(1000.0 * wall_s / max(st_s.completed, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage, f64 accumulation (QR and LSQR in f64)",
+        "data": "synthetic (seeded device pools; row windows with N(0,1) entries, b = A x + 1e-3 N(0,1))",
+        "config": {"workload": SERVE_WORKLOAD, "requests": len(reqs), "rate_per_s": args.rate,
+                   "m": "floor(2^U[12,20])", "n": [16, 32, 64, 128, 256], "d": "4n",
+                   "rtol": args.rtol, "max_slots": args.slots, "chunk_iters": args.chunk,
+                   "parallelism": "single GPU"},
+        "open_loop": {"solves_per_s": round(st_o.completed / wall_o, 2),
+                      "p50_ms": round(st_o.p50_ms, 3), "p99_ms": round(st_o.p99_ms, 3),
+                      "mean_ms": round(st_o.mean_ms, 3), "peak_slots": st_o.peak_slots},
+        "saturation": {"solves_per_s": round(sat, 2), "p50_ms": round(st_s.p50_ms, 3),
+                       "p99_ms": round(st_s.p99_ms, 3), "rounds": int(st_s.rounds),
+                       "peak_pool_bytes": int(st_s.peak_pool_bytes)},
+        "baselines": base,
+        "speedup_vs_per_problem_fp64": round(sat / base["per_problem_fp64"]["solves_per_s"], 3),
+        "max_RE_sample": worst,
+        "RE_sample_size": checked,
+        "nonzero_status": bad[:10],
+        "roofline": {"bound": "hbm", "achieved": round(tot / wall_s / 1e9, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(tot / wall_s / 1e9 / HBM_PEAK_GBPS, 4),
+                     "traffic": None, "kernel": "whole job (sketch + LSQR passes, algorithmic bytes)"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="illcond_fp32_4194304x256", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="illcond_fp32_4194304x256",
+                    choices=sorted(WORKLOADS) + [SERVE_WORKLOAD])
+    ap.add_argument("--requests", type=int, default=10000, help="serving mix: requests")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving mix: arrivals per second")
+    ap.add_argument("--slots", type=int, default=64, help="serving mix: admitted requests")
+    ap.add_argument("--chunk", type=int, default=4, help="serving mix: iterations per round")
+    ap.add_argument("--baseline-requests", type=int, default=400)
+    ap.add_argument("--cpu-requests", type=int, default=20)
     ap.add_argument("--m", type=int, default=0, help="override the workload's row count")
     ap.add_argument("--rtol", type=float, default=1e-6)
-    ap.add_argument("--max-iters", type=int, default=80)
+    ap.add_argument("--max-iters", type=int, default=100)
     ap.add_argument("--cpu-rows", type=int, default=1 << 19)
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
@@ -99,6 +259,10 @@ def main():
         print("bench.py measures a single GPU: the sketch-and-solve path here runs on one "
               "device; --gpus above 1 is not supported.", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == SERVE_WORKLOAD:
+        serve_main(args)
+        return
 
     import numpy as np
     import torch

@@ -160,6 +160,34 @@ def serving_requests(count: int, rate: float, seed: int, log2_m=(12.0, 20.0),
              "seed": int(seeds[i])} for i in range(count)]
 
 
+def serving_pool(rows: int = 1 << 20, n_choices=(16, 32, 64, 128, 256), seed: int = 0,
+                 noise: float = 1e-3, device="cuda", fp64: bool = False):
+    """Device-resident data for the serving mix (the whole run does not fit in
+    memory as separate matrices).  For each n: A_n (rows x n, N(0,1), fp32, or
+    fp64 with fp64=True), x_n ~ N(0, I) and b_n = A_n x_n + noise N(0, I),
+    drawn with torch's seeded generator on the device.  A request (m, n) uses
+    the contiguous row window request_window() of A_n, b_n, which is itself
+    a problem with i.i.d. N(0,1) entries and b = A x_n + noise."""
+    import torch
+    g = torch.Generator(device=device)
+    out = {}
+    for k, n in enumerate(n_choices):
+        g.manual_seed(seed * 1000 + k)
+        A = torch.randn(rows, n, generator=g, device=device, dtype=torch.float32)
+        x = torch.randn(n, generator=g, device=device, dtype=torch.float64)
+        e = torch.randn(rows, generator=g, device=device, dtype=torch.float64)
+        Ad = A.double() if fp64 else None
+        b64 = (Ad if fp64 else A.double()) @ x + noise * e
+        out[n] = dict(A=Ad if fp64 else A, b=b64 if fp64 else b64.float(), x=x.cpu().numpy())
+        del e
+    return out
+
+
+def request_window(req: dict, rows: int):
+    """First row of the request's window in its pool (deterministic)."""
+    return int(req["seed"]) % (rows - int(req["m"]) + 1)
+
+
 def paper_benchmark(m: int, n: int, seed: int, cond: float = 1e10, beta: float = 1e-10) -> Dense:
     """Sec. 3.1 family: A = U diag(sigma) V^T with Haar U (m x n) and V (n x n),
     sigma log-spaced 1 .. 1/cond; b = A x + beta r_perp with r_perp a unit
