@@ -277,6 +277,38 @@ sns_status sns_serve_stats_get(sns_server* srv, sns_serve_stats* out);
  * server (not the pool). */
 sns_status sns_serve_destroy(sns_server* srv);
 
+/* ------------------------------------------------------------ autotuner --
+ * The fused refinement pass has launch-shape parameters (lanes per row,
+ * 16-byte chunks per lane, work-groups, rows per step).  The plan for a
+ * problem is taken from a tuning table entry matching its dtype, n and m
+ * range; without one, a built-in rule is used.  The tuner times every valid
+ * candidate on the caller's matrix with HIP events and reports the fastest;
+ * a driver (paper_2409_14309_amd/autotune.py) sweeps shapes and saves the
+ * table.  A plan fixes the order of the per-group partial sums, so results
+ * are reproducible for a given table. */
+typedef struct {
+  int dtype;             /* sns_dtype */
+  int n;
+  int64_t m_lo, m_hi;    /* rows covered, inclusive */
+  int lpr, nch, grid, unroll;
+  double us;             /* measured time of one pass (informational) */
+} sns_tune_entry;
+
+/* Workspace for sns_tune_pass on A. */
+sns_status sns_tune_workspace_size(const sns_matrix* A, size_t* bytes);
+/* Time every candidate plan of the pass on A (dense, device data; `reps`
+ * timed launches each after one warm-up) and write the fastest to *best
+ * (m_lo = m_hi = A->m).  Synchronous. */
+sns_status sns_tune_pass(const sns_matrix* A, int reps, void* workspace, size_t ws_bytes,
+                         sns_tune_entry* best, void* stream);
+/* The table: add or replace the entry with the same dtype, n, m_lo, m_hi;
+ * clear; load (appends; text lines "dtype n m_lo m_hi lpr nch grid unroll us",
+ * '#' comments) and save.  Thread-safe. */
+sns_status sns_tune_set(const sns_tune_entry* e);
+sns_status sns_tune_clear(void);
+sns_status sns_tune_load(const char* path);
+sns_status sns_tune_save(const char* path);
+
 /* Kernel timing (tracing support).  While enabled, every kernel the library
  * launches is bracketed by two HIP events on its stream; sns_timing_summary
  * waits for the recorded launches and writes one line per kernel name,

@@ -65,6 +65,14 @@ class ServeStats(C.Structure):
                 ("peak_pool_bytes", C.c_size_t), ("peak_slots", C.c_int), ("rounds", C.c_uint64)]
 
 
+class TuneEntry(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("n", C.c_int), ("m_lo", C.c_int64), ("m_hi", C.c_int64),
+                ("lpr", C.c_int), ("nch", C.c_int), ("grid", C.c_int), ("unroll", C.c_int),
+                ("us", C.c_double)]
+
+
+TUNING_PATH = os.path.join(HERE, "tuning.txt")
+
 _lib = None
 
 _SIGS = {
@@ -97,6 +105,13 @@ _SIGS = {
     "sns_serve_wait": (C.c_int, [C.c_void_p, C.c_uint64, C.POINTER(Info)]),
     "sns_serve_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ServeStats)]),
     "sns_serve_destroy": (C.c_int, [C.c_void_p]),
+    "sns_tune_workspace_size": (C.c_int, [C.POINTER(Matrix), C.POINTER(C.c_size_t)]),
+    "sns_tune_pass": (C.c_int, [C.POINTER(Matrix), C.c_int, C.c_void_p, C.c_size_t,
+                                C.POINTER(TuneEntry), C.c_void_p]),
+    "sns_tune_set": (C.c_int, [C.POINTER(TuneEntry)]),
+    "sns_tune_clear": (C.c_int, []),
+    "sns_tune_load": (C.c_int, [C.c_char_p]),
+    "sns_tune_save": (C.c_int, [C.c_char_p]),
     "sns_timing_enable": (None, [C.c_int]),
     "sns_timing_reset": (None, []),
     "sns_timing_summary": (C.c_int, [C.c_char_p, C.c_size_t]),
@@ -109,6 +124,12 @@ def load(path: str | None = None):
     if _lib is not None:
         return _lib
     p = path or LIB_PATH
+    # torch brings its own HIP runtime: load it first so that libsns binds to
+    # the same runtime as the device memory it is handed
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(p):
         raise RuntimeError(f"libsns.so not built ({p}); run `python -m paper_2409_14309_amd.build`")
     lib = C.CDLL(p)
@@ -117,6 +138,9 @@ def load(path: str | None = None):
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    # the tuning table written by the autotuner, when present
+    if os.path.exists(TUNING_PATH):
+        _check(lib.sns_tune_load(TUNING_PATH.encode()), "sns_tune_load")
     return lib
 
 
@@ -304,6 +328,38 @@ def sns_serve_stats_get(srv) -> ServeStats:
 
 def sns_serve_destroy(srv):
     _check(load().sns_serve_destroy(srv), "sns_serve_destroy")
+
+
+# ---------------------------------------------------------- autotuner ----
+
+def sns_tune_workspace_size(A: Matrix) -> int:
+    n = C.c_size_t(0)
+    _check(load().sns_tune_workspace_size(C.byref(A), C.byref(n)), "sns_tune_workspace_size")
+    return n.value
+
+
+def sns_tune_pass(A: Matrix, reps: int, workspace, stream=None) -> TuneEntry:
+    e = TuneEntry()
+    _check(load().sns_tune_pass(C.byref(A), reps, _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), C.byref(e),
+                                _stream(stream)), "sns_tune_pass")
+    return e
+
+
+def sns_tune_set(e: TuneEntry):
+    _check(load().sns_tune_set(C.byref(e)), "sns_tune_set")
+
+
+def sns_tune_clear():
+    _check(load().sns_tune_clear(), "sns_tune_clear")
+
+
+def sns_tune_load(path: str):
+    _check(load().sns_tune_load(path.encode()), "sns_tune_load")
+
+
+def sns_tune_save(path: str):
+    _check(load().sns_tune_save(path.encode()), "sns_tune_save")
 
 
 # ------------------------------------------------------------- timing ----

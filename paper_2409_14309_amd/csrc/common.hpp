@@ -6,10 +6,18 @@
 
 #include "../../include/sns.h"
 
-#define SNS_HIP_TRY(expr)                                   \
-  do {                                                      \
-    hipError_t e_ = (expr);                                 \
-    if (e_ != hipSuccess) return SNS_ERR_HIP;               \
+namespace sns {
+// Reports a failed HIP call on stderr when SNS_DEBUG=1 is set (trace.hip).
+void report_hip_error(hipError_t e, const char* what, const char* file, int line);
+}  // namespace sns
+
+#define SNS_HIP_TRY(expr)                                                   \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      ::sns::report_hip_error(e_, #expr, __FILE__, __LINE__);               \
+      return SNS_ERR_HIP;                                                   \
+    }                                                                       \
   } while (0)
 
 namespace sns {

@@ -273,6 +273,15 @@ struct LsqrPlan {
   int unroll = 1;   // rows per slot and step (1 or 2)
 };
 LsqrPlan make_lsqr_plan(const sns_matrix& A);
+// Tuning-table lookup (tune.hip): the entry for (dtype, n, m), if any.
+bool tune_lookup(sns_dtype dt, int64_t n, int64_t m, LsqrPlan* p);
+// Whether the pass is instantiated for (lpr, nch).
+bool lsqr_plan_valid(int lpr, int nch);
+// Time the fused pass on A with plan p: average microseconds over `reps`
+// launches after one warm-up, on a state that never stops.
+sns_status time_lsqr_pass(const sns_matrix& A, const LsqrPlan& p, int reps, void* ws,
+                          size_t ws_bytes, hipStream_t st, double* us);
+size_t tune_workspace_bytes(const sns_matrix& A);
 size_t lsqr_workspace_bytes(const sns_matrix& A, const LsqrPlan& p);
 void carve_lsqr(Carve& c, const sns_matrix& A, const LsqrPlan& p, LsqrBufs& l);
 struct LsqrArgs {

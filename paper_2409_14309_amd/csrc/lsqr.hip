@@ -591,12 +591,15 @@ LsqrPlan make_lsqr_plan(const sns_matrix& A) {
   if (g < 1) g = 1;
   p.grid = (int)g;
   p.unroll = 1;
+  LsqrPlan t;
+  if (tune_lookup(A.dtype, n, A.m, &t) && lsqr_plan_valid(t.lpr, t.nch) &&
+      (int64_t)t.lpr * t.nch * vw >= n && t.grid >= 1 && t.grid <= 65535 &&
+      (t.unroll == 1 || t.unroll == 2))
+    p = t;
   if (const char* e = getenv("SNS_LSQR_PLAN")) {
     int a = 0, b = 0, c = 0, d = 1;
     if (sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d) >= 3) {
-      const bool lpr_ok = a == 4 || a == 8 || a == 16 || a == 32 || a == 64;
-      const bool nch_ok = b == 1 || b == 2 || b == 4 || b == 8;
-      if (lpr_ok && nch_ok && (int64_t)a * b * vw >= n && c >= 1 && c <= 65535) {
+      if (lsqr_plan_valid(a, b) && (int64_t)a * b * vw >= n && c >= 1 && c <= 65535) {
         p.lpr = a;
         p.nch = b;
         p.grid = c;
@@ -605,6 +608,95 @@ LsqrPlan make_lsqr_plan(const sns_matrix& A) {
     }
   }
   return p;
+}
+
+bool lsqr_plan_valid(int lpr, int nch) {
+  switch (lpr) {
+    case 4: return nch == 1 || nch == 2 || nch == 4;
+    case 8: return nch == 4;
+    case 16:
+    case 32: return nch == 1 || nch == 2 || nch == 4;
+    case 64: return nch == 1 || nch == 2 || nch == 4 || nch == 8;
+    default: return false;
+  }
+}
+
+constexpr int kTuneMaxGrid = 4096;
+
+size_t tune_workspace_bytes(const sns_matrix& A) {
+  const size_t es = A.dtype == SNS_F64 ? 8 : 4;
+  Carve c(nullptr, 0);
+  c.take<char>((size_t)A.m * es);
+  c.take<double>((size_t)kTuneMaxGrid * A.n);
+  c.take<double>((size_t)kTuneMaxGrid);
+  c.take<double>((size_t)6 * A.n);
+  c.take<LsqrState>(1);
+  c.take<char>(4096);
+  return c.off;
+}
+
+sns_status time_lsqr_pass(const sns_matrix& A, const LsqrPlan& p, int reps, void* ws,
+                          size_t ws_bytes, hipStream_t st, double* us) {
+  if (!lsqr_plan_valid(p.lpr, p.nch) || p.grid < 1 || p.grid > kTuneMaxGrid || reps < 1)
+    return SNS_ERR_INVALID_ARG;
+  const size_t es = A.dtype == SNS_F64 ? 8 : 4;
+  const int n = (int)A.n;
+  Carve c(ws, ws_bytes);
+  LsqrBufs l{};
+  l.u = c.take<char>((size_t)A.m * es);
+  l.zpart = c.take<double>((size_t)kTuneMaxGrid * n);
+  l.npart = c.take<double>((size_t)kTuneMaxGrid);
+  l.vecs = c.take<double>((size_t)6 * n);
+  l.state = c.take<LsqrState>(1);
+  char* args = c.take<char>(4096);
+  if (!c.ok()) return SNS_ERR_OUT_OF_MEMORY;
+  LsqrState h{};
+  h.gamma = 0.5;
+  h.iter = 0;  // reads u, not b
+  h.max_iters = 1 << 30;
+  SNS_HIP_TRY(hipMemcpyAsync(l.state, &h, sizeof(h), hipMemcpyHostToDevice, st));
+  SNS_HIP_TRY(hipMemsetAsync(l.u, 0, (size_t)A.m * es, st));
+  SNS_HIP_TRY(hipMemsetAsync(l.vecs, 0, sizeof(double) * 6 * n, st));
+  LsqrArgs a{};
+  a.A = A.values;
+  a.ld = A.ld;
+  a.m = A.m;
+  a.n = n;
+  a.grid = p.grid;
+  a.b = l.u;
+  a.u = l.u;
+  a.zpart = l.zpart;
+  a.npart = l.npart;
+  a.vecs = l.vecs;
+  a.st = static_cast<LsqrState*>(l.state);
+  ArgTable t(args);
+  const LsqrJob j = build_lsqr_job(t, std::vector<LsqrProb>{LsqrProb{p, a}}, A.dtype == SNS_F64);
+  if (t.bytes() > 4096) return SNS_ERR_OUT_OF_MEMORY;
+  sns_status e = t.upload(st);
+  if (e != SNS_OK) return e;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SNS_HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SNS_ERR_HIP;
+  }
+  auto pass = [&]() {
+    if (j.f64) launch_pass_v<double, 2>(j.cls[0], st);
+    else launch_pass_v<float, 4>(j.cls[0], st);
+  };
+  pass();
+  float ms = 0.f;
+  hipError_t he = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && he == hipSuccess; ++r) pass();
+  if (he == hipSuccess) he = hipEventRecord(e1, st);
+  if (he == hipSuccess) he = hipEventSynchronize(e1);
+  if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  SNS_HIP_TRY(he);
+  SNS_HIP_TRY(hipGetLastError());
+  *us = 1000.0 * ms / reps;  // host h stayed alive until the synchronisation above
+  return SNS_OK;
 }
 
 size_t lsqr_workspace_bytes(const sns_matrix& A, const LsqrPlan& p) {

@@ -85,6 +85,14 @@ void check_env(Registry& r) {
 
 }  // namespace
 
+void report_hip_error(hipError_t e, const char* what, const char* file, int line) {
+  static const bool on = [] {
+    const char* v = getenv("SNS_DEBUG");
+    return v && v[0] == '1';
+  }();
+  if (on) fprintf(stderr, "libsns: %s failed: %s (%s:%d)\n", what, hipGetErrorString(e), file, line);
+}
+
 void timing_begin(const char* name, hipStream_t s) {
   Registry& r = reg();
   std::lock_guard<std::mutex> g(r.mu);

@@ -94,3 +94,39 @@ def test_device_gaussian_table_matches_oracle_bits():
     ref = np.array([struct.unpack("<I", struct.pack("<f", np.float32(v)))[0] >> 16
                     for v in gaussian_table()], dtype=np.uint16)
     assert np.array_equal(got, ref)
+
+
+def test_tuning_table_round_trip(tmp_path):
+    """Host-only: entries survive save/clear/load; bad entries and malformed
+    files are refused and leave the table unchanged."""
+    import paper_2409_14309_amd as sns
+    sns.load()
+    sns.sns_tune_clear()
+    a = sns.TuneEntry(0, 256, 1, 1 << 20, 16, 4, 512, 1, 123.5)
+    b = sns.TuneEntry(1, 50, 4096, 65535, 16, 1, 64, 2, 7.25)
+    sns.sns_tune_set(a)
+    sns.sns_tune_set(b)
+    sns.sns_tune_set(sns.TuneEntry(0, 256, 1, 1 << 20, 32, 4, 1024, 2, 99.0))  # replaces a
+    p1 = tmp_path / "t1.txt"
+    sns.sns_tune_save(str(p1))
+    sns.sns_tune_clear()
+    sns.sns_tune_load(str(p1))
+    p2 = tmp_path / "t2.txt"
+    sns.sns_tune_save(str(p2))
+    assert p1.read_text() == p2.read_text()
+    rows = [ln.split() for ln in p1.read_text().splitlines() if not ln.startswith("#")]
+    assert rows == [["0", "256", "1", "1048576", "32", "4", "1024", "2", "99.000"],
+                    ["1", "50", "4096", "65535", "16", "1", "64", "2", "7.250"]]
+    import pytest
+    with pytest.raises(sns.SnsError):
+        sns.sns_tune_set(sns.TuneEntry(0, 64, 1, 10, 8, 2, 64, 1, 0.0))  # (8, 2) not a pass shape
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 64 1 10 16 4 64 1 1.0\n0 64 oops\n")
+    with pytest.raises(sns.SnsError):
+        sns.sns_tune_load(str(bad))
+    p3 = tmp_path / "t3.txt"
+    sns.sns_tune_save(str(p3))
+    assert p3.read_text() == p1.read_text()
+    sns.sns_tune_clear()
+    if os.path.exists(sns._binding.TUNING_PATH):
+        sns.sns_tune_load(sns._binding.TUNING_PATH)
