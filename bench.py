@@ -46,11 +46,24 @@ def log(msg):
 
 
 def kernel_source_hash(*names) -> str:
+    """Hash of the files a kernel's code depends on (paths relative to the
+    package), so that stored counter readings are used only for the code
+    they were taken on."""
     h = hashlib.sha256()
     for nm in names:
-        with open(os.path.join(ROOT, "paper_2409_14309_amd", "csrc", nm), "rb") as f:
-            h.update(f.read())
+        p = os.path.join(ROOT, "paper_2409_14309_amd", nm)
+        if os.path.exists(p):
+            with open(p, "rb") as f:
+                h.update(f.read())
     return h.hexdigest()[:16]
+
+
+# files whose content determines each timed kernel's code and launch shape
+KERNEL_SOURCES = {
+    "lsqr_pass": ("csrc/lsqr.hip", "csrc/kernels.hpp", "csrc/common.hpp", "tuning.txt"),
+    "cs_gather": ("csrc/countsketch.hip", "csrc/kernels.hpp", "csrc/common.hpp"),
+    "gauss_mfma": ("csrc/gauss.hip", "csrc/kernels.hpp", "csrc/common.hpp"),
+}
 
 
 def measured_traffic(kernel: str, src_hash: str):
@@ -236,6 +249,20 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration(nbytes: int):
+    """Five device-to-device copies of a known size: under rocprofv3 --pmc
+    their FETCH_SIZE / WRITE_SIZE readings convert the counters of the
+    library's kernels into bytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +276,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=4, help="serving mix: iterations per round")
     ap.add_argument("--baseline-requests", type=int, default=400)
     ap.add_argument("--cpu-requests", type=int, default=20)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run 5 plain device copies of BYTES bytes (scales HBM counters)")
     ap.add_argument("--m", type=int, default=0, help="override the workload's row count")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--max-iters", type=int, default=100)
@@ -262,6 +291,9 @@ def main():
 
     if args.workload == SERVE_WORKLOAD:
         serve_main(args)
+        return
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
         return
 
     import numpy as np
@@ -340,7 +372,6 @@ def main():
     }
     # Gaussian sketch: 2 d m n flops for G A plus 2 d m for G b
     flops_per = {"gauss_mfma": 2.0 * d * m * n + 2.0 * d * m}
-    src = {"lsqr_pass": ("lsqr.hip",), "cs_gather": ("countsketch.hip",), "gauss_mfma": ("gauss.hip",)}
 
     def roofline(kname):
         cnt, tot, avg_us = kt[kname]
@@ -348,7 +379,7 @@ def main():
             ach = bytes_per[kname] / (avg_us * 1e-6) / 1e9
             return {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
-                    "traffic": measured_traffic(kname, kernel_source_hash(*src[kname])),
+                    "traffic": measured_traffic(kname, kernel_source_hash(*KERNEL_SOURCES[kname])),
                     "bytes_per_launch": bytes_per[kname], "avg_launch_us": avg_us, "launches": cnt}
         if kname in flops_per:
             ach = flops_per[kname] / (avg_us * 1e-6) / 1e12
