@@ -235,12 +235,13 @@ QrArgs qr_args(int64_t d, int64_t n, const void* SA, int64_t ld_sa, const void* 
 struct QrJob {
   bool f64 = false;  // SA element type
   const QrArgs* all = nullptr;
-  Map mload{}, mone{};
-  uint32_t nload = 0;
+  Map mload{}, mone{}, mextract{};
+  uint32_t nload = 0, nextract = 0;
   int count = 0;
   int64_t maxn = 0;
   struct Cls {
     int cfg;  // panel configuration index
+    int cb;   // trailing columns per work item
     const QrArgs* args;
     Map mone, mtrail;
     uint32_t ntrail;

@@ -10,9 +10,11 @@ namespace sns {
 // Sum NB values per thread over a work-group of NT threads; tot[0..NB) (LDS)
 // gets the totals, visible to all threads on return.  red: LDS of NB * NT
 // doubles.  The values are transposed through LDS: value c is summed by the
-// P = NT / NB consecutive threads of group c, each adding NB stored entries
-// in order, and the group finishes with an xor-shuffle over its P lanes.  The
-// order is fixed, so the result is reproducible.
+// P = NT / NB consecutive threads of group c, thread p adding the stored
+// entries p, p + P, ..., p + (NB - 1) P in order (consecutive lanes read
+// consecutive words, so the reads are free of bank conflicts), and the group
+// finishes with an xor-shuffle over its P lanes.  The order is fixed, so the
+// result is reproducible.
 template <int NB, int NT>
 __device__ __forceinline__ void block_reduce_multi(const double (&g)[NB], double* red,
                                                    double* tot) {
@@ -26,7 +28,7 @@ __device__ __forceinline__ void block_reduce_multi(const double (&g)[NB], double
   const int c = t / P, p = t % P;
   double s = 0.0;
 #pragma unroll
-  for (int q = 0; q < NB; ++q) s += red[c * NT + p * NB + q];
+  for (int q = 0; q < NB; ++q) s += red[c * NT + q * P + p];
 #pragma unroll
   for (int off = PW / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
   if constexpr (P <= 64) {

@@ -10,7 +10,9 @@
 //                 (for the rank-1 update) and with the earlier Householder
 //                 vectors (for the compact-WY factor T).
 //   k_qr_trailing applies (I - V T V^T)^T to the trailing columns, Sb
-//                 included; each work-group owns 8 columns.
+//                 included; each work-group owns one or two columns.
+// then k_qr_extract copies R out (tiled transposes) and k_qr_finish checks
+// rank and finiteness and solves R x0 = c on one work-group.
 // Reflector convention (LAPACK): beta = -sign(alpha) ||x|| (sign(0) = +1),
 // tau = (beta - alpha) / beta, v = x / (alpha - beta) with v[0] = 1.
 #include "common.hpp"
@@ -21,7 +23,6 @@ namespace sns {
 
 namespace {
 
-constexpr int kPanelThreads = 512;
 
 // M[j * d + i] = SA[i * ld + j] (j < n), M[n * d + i] = Sb[i], via 32x32 tiles
 // (a work item is one tile).  The first tile also clears the scalar flags.
@@ -56,11 +57,14 @@ __global__ void k_qr_load(const QrArgs* __restrict__ P, Map mp) {
 
 // One Householder step of the panel, column K (a compile-time index so the
 // register array P is never indexed at run time).
-template <int MAXR, int NB, int K>
-__device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t j0, int64_t d,
+template <int MAXR, int NB, int NT, int K>
+__device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t j0,
                                            double* red, double* tot, double* piv, double* Ts,
                                            double* __restrict__ tau, double* __restrict__ flags) {
   const int64_t jk = j0 + K;  // pivot row, owned by thread K (r = 0)
+  // the pivot row alternates between two LDS buffers: step K + 1 may write
+  // its row while a slower wave still reads this one (no barrier ends a step)
+  piv += (K & 1) * NB;
   // partial sums over the rows below the pivot, x = column K there:
   // G_c = x . M[:, c] (c >= K) and Y_a = x . V[:, a] (a < K).  Rows at or
   // above the pivot contribute x = 0; rows past d hold zeros.
@@ -69,7 +73,7 @@ __device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t
   for (int c = 0; c < NB; ++c) g[c] = 0.0;
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
-    const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
+    const int64_t i = j0 + t + (int64_t)NT * r;
     const double x = i > jk ? P[r][K] : 0.0;
 #pragma unroll
     for (int c = 0; c < NB; ++c) g[c] = fma(x, P[r][c], g[c]);
@@ -78,7 +82,7 @@ __device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t
 #pragma unroll
     for (int c = 0; c < NB; ++c) piv[c] = P[0][c];
   }
-  block_reduce_multi<NB, kPanelThreads>(g, red, tot);  // its barriers also publish piv
+  block_reduce_multi<NB, NT>(g, red, tot);  // its barriers also publish piv
   const double alpha = piv[K];
   const double nu = sqrt(alpha * alpha + tot[K]);
   double beta = 0.0, tk = 0.0, scale = 0.0;
@@ -95,7 +99,7 @@ __device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t
   for (int c = K + 1; c < NB; ++c) w[c] = piv[c] + scale * tot[c];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
-    const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
+    const int64_t i = j0 + t + (int64_t)NT * r;
     const bool below = i > jk, at = i == jk;
     const double v = P[r][K] * scale;
     const double f = below ? tk * v : (at ? tk : 0.0);
@@ -115,33 +119,33 @@ __device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t
     tau[jk] = tk;
     if (!isfinite(nu)) flags[2] = 1.0;
   }
-  __syncthreads();
+  // No barrier here: the next step's reduction barriers order every later
+  // use of red, tot and Ts; each thread's Ts column entries are its own.
 }
 
-template <int MAXR, int NB, int K>
-__device__ __forceinline__ void panel_steps(double (&P)[MAXR][NB], int t, int64_t j0, int64_t d,
-                                            int nbw, double* red, double* tot, double* piv,
-                                            double* Ts, double* __restrict__ tau,
-                                            double* __restrict__ flags) {
+template <int MAXR, int NB, int NT, int K>
+__device__ __forceinline__ void panel_steps(double (&P)[MAXR][NB], int t, int64_t j0, int nbw,
+                                            double* red, double* tot, double* piv, double* Ts,
+                                            double* __restrict__ tau, double* __restrict__ flags) {
   if constexpr (K < NB) {
     if (K < nbw) {
-      panel_step<MAXR, NB, K>(P, t, j0, d, red, tot, piv, Ts, tau, flags);
-      panel_steps<MAXR, NB, K + 1>(P, t, j0, d, nbw, red, tot, piv, Ts, tau, flags);
+      panel_step<MAXR, NB, NT, K>(P, t, j0, red, tot, piv, Ts, tau, flags);
+      panel_steps<MAXR, NB, NT, K + 1>(P, t, j0, nbw, red, tot, piv, Ts, tau, flags);
     }
   }
 }
 
 // Factor panel columns [j0, j0 + nbw) of M over rows [j0, d), nbw =
-// min(NB, n - j0).  Thread t owns rows j0 + t + 512 r, r < MAXR.  Writes R
+// min(NB, n - j0).  Thread t owns rows j0 + t + NT r, r < MAXR.  Writes R
 // entries, Householder vectors (below the diagonal), tau, and T (NB x NB,
 // column-major, upper).  One work item per problem; problems with n <= j0
 // have nothing to do.
-template <int MAXR, int NB>
-__global__ __launch_bounds__(kPanelThreads) void k_qr_panel(const QrArgs* __restrict__ P, Map mp,
+template <int MAXR, int NB, int NT>
+__global__ __launch_bounds__(NT) void k_qr_panel(const QrArgs* __restrict__ P, Map mp,
                                                             int64_t j0) {
-  __shared__ double red[kPanelThreads * NB];
+  __shared__ double red[NT * NB];
   __shared__ double tot[NB];
-  __shared__ double piv[NB];
+  __shared__ double piv[2 * NB];
   __shared__ double Ts[NB * NB];
   const int t = threadIdx.x;
   const uint32_t it = blockIdx.x;
@@ -154,32 +158,37 @@ __global__ __launch_bounds__(kPanelThreads) void k_qr_panel(const QrArgs* __rest
   double Pn[MAXR][NB];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
-    const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
+    const int64_t i = j0 + t + (int64_t)NT * r;
 #pragma unroll
     for (int c = 0; c < NB; ++c) Pn[r][c] = (i < d && c < nbw) ? M[(j0 + c) * d + i] : 0.0;
   }
-  for (int e = t; e < NB * NB; e += kPanelThreads) Ts[e] = 0.0;
+  for (int e = t; e < NB * NB; e += NT) Ts[e] = 0.0;
   __syncthreads();
-  panel_steps<MAXR, NB, 0>(Pn, t, j0, d, nbw, red, tot, piv, Ts, a.tau, a.scal);
+  panel_steps<MAXR, NB, NT, 0>(Pn, t, j0, nbw, red, tot, piv, Ts, a.tau, a.scal);
+  __syncthreads();  // Ts complete
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
-    const int64_t i = j0 + t + (int64_t)kPanelThreads * r;
+    const int64_t i = j0 + t + (int64_t)NT * r;
     if (i < d)
 #pragma unroll
       for (int c = 0; c < NB; ++c)
         if (c < nbw) M[(j0 + c) * d + i] = Pn[r][c];
   }
-  for (int e = t; e < NB * NB; e += kPanelThreads) a.T[e] = Ts[e];
+  for (int e = t; e < NB * NB; e += NT) a.T[e] = Ts[e];
 }
 
 // C <- (I - V T V^T)^T C = C - V (T^T (V^T C)) for the trailing columns
 // [j0 + nbw, n] (Sb is the last one), rows [j0, d).  A work-group owns CB
-// columns.  Sweep 1: every thread accumulates its rows' share of W = V^T C in
-// registers (independent loads, no barriers); W is reduced over the group
-// through LDS in a fixed order and multiplied by T^T.  Sweep 2 re-reads V and
+// columns (trail_cb).  Sweep 1: every thread accumulates its rows' share of
+// W = V^T C in registers (independent loads, no barriers); W is reduced over
+// the group through LDS in a fixed order and multiplied by T^T.  Sweep 2 re-reads V and
 // C and applies the update.
 constexpr int kTrailThreads = 256;
-constexpr int kTrailCB = 4;
+
+// Columns per trailing work item.  It depends only on the problem's own n
+// (the reduction order, hence the rounding, follows it): one column per
+// work-group keeps hundreds of work-groups busy for the n of the workloads.
+int trail_cb(int64_t n) { return n > 2048 ? 2 : 1; }
 
 template <int NB>
 __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t d, int64_t j0,
@@ -191,10 +200,10 @@ __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t 
 
 // One work item per CB trailing columns; a problem owns ceil(n / CB) items,
 // of which the first ceil(ntr / CB) have columns at step j0.
-template <int NB>
+template <int NB, int CB>
 __global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(const QrArgs* __restrict__ P,
                                                                Map mp, int64_t j0) {
-  constexpr int CB = kTrailCB, NT = kTrailThreads, NV = NB * CB;
+  constexpr int NT = kTrailThreads, NV = NB * CB;
   __shared__ double red[NV * NT];
   __shared__ double W[NV];
   __shared__ double Wt[NV];
@@ -260,9 +269,44 @@ __global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(const QrArgs* __r
   }
 }
 
-// rho, R (column-major copy and optional row-major output), rank and
-// finiteness checks, and x0 = R^{-1} c.  One work item (1024 threads) per
-// problem.
+// R out of the factored M: Rc (column-major, ld n), Rr and the optional Rout
+// (row-major) and invd = 1 / diag, by 32 x 32 tiles transposed through LDS
+// (a work item is one tile; tiles below the diagonal write zeros).
+__global__ void k_qr_extract(const QrArgs* __restrict__ P, Map mp) {
+  __shared__ double tile[32][33];
+  const uint32_t it = blockIdx.x;
+  if (it >= mp.off[mp.nprob]) return;
+  const int pi = map_find(mp, it);
+  const QrArgs& a = P[pi];
+  const uint32_t loc = it - mp.off[pi];
+  const int64_t d = a.d, n = a.n;
+  const double* __restrict__ M = a.M;
+  const uint32_t tiles = (uint32_t)((n + 31) / 32);
+  const int64_t i0 = (int64_t)(loc % tiles) * 32, j0 = (int64_t)(loc / tiles) * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;  // 32 x 8
+  for (int c = ty; c < 32; c += 8) {
+    const int64_t j = j0 + c, i = i0 + tx;
+    double v = 0.0;
+    if (i < n && j < n) {
+      if (i <= j) v = M[j * d + i];
+      a.R[j * n + i] = v;
+    }
+    tile[c][tx] = v;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    if (i < n && j < n) {
+      const double v = tile[tx][r];
+      a.Rr[i * n + j] = v;
+      if (a.Rout) a.Rout[i * n + j] = v;
+    }
+  }
+  if (i0 == j0 && ty == 0 && i0 + tx < n) a.invd[i0 + tx] = 1.0 / M[(i0 + tx) * d + i0 + tx];
+}
+
+// rho, rank and finiteness checks, and x0 = R^{-1} c (R and invd from
+// k_qr_extract).  One work item (1024 threads) per problem.
 __device__ __forceinline__ void qr_finish_item(const QrArgs& a, double* sh) {
   const int64_t d = a.d, n = a.n;
   const double* __restrict__ M = a.M;
@@ -276,14 +320,6 @@ __device__ __forceinline__ void qr_finish_item(const QrArgs& a, double* sh) {
     s += v * v;
   }
   const double rho = sqrt(block_sum(s, red));
-  for (int64_t e = t; e < n * n; e += nt) {
-    const int64_t j = e / n, i = e % n;  // Rc[j * n + i] = R[i, j]
-    const double v = i <= j ? M[j * d + i] : 0.0;
-    a.R[e] = v;
-    a.Rr[i * n + j] = v;
-    if (a.Rout) a.Rout[i * n + j] = v;
-  }
-  for (int64_t i = t; i < n; i += nt) a.invd[i] = 1.0 / M[i * d + i];
   double mx = 0.0;
   bool bad = false;
   for (int64_t i = t; i < n; i += nt) {
@@ -331,15 +367,21 @@ int qr_cfg(int64_t d) {
   return 4;
 }
 
-template <int MAXR, int NB>
+template <int MAXR, int NB, int NT, int CB>
 void run_panels(const QrJob::Cls& c, hipStream_t st) {
   for (int64_t j0 = 0; j0 < c.maxn; j0 += NB) {
-    SNS_LAUNCH("qr_panel", (k_qr_panel<MAXR, NB>), dim3(grid_for((uint32_t)c.count)),
-               dim3(kPanelThreads), 0, st, c.args, c.mone, j0);
+    SNS_LAUNCH("qr_panel", (k_qr_panel<MAXR, NB, NT>), dim3(grid_for((uint32_t)c.count)),
+               dim3(NT), 0, st, c.args, c.mone, j0);
     if (c.ntrail)
-      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB>), dim3(grid_for(c.ntrail)), dim3(kTrailThreads),
-                 0, st, c.args, c.mtrail, j0);
+      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB, CB>), dim3(grid_for(c.ntrail)),
+                 dim3(kTrailThreads), 0, st, c.args, c.mtrail, j0);
   }
+}
+
+template <int MAXR, int NB, int NT>
+void run_panels_cb(const QrJob::Cls& c, hipStream_t st) {
+  if (c.cb == 2) run_panels<MAXR, NB, NT, 2>(c, st);
+  else run_panels<MAXR, NB, NT, 1>(c, st);
 }
 
 }  // namespace
@@ -388,30 +430,34 @@ QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
   j.f64 = f64;
   j.count = (int)a.size();
   if (a.empty()) return j;
-  std::vector<uint32_t> load, one;
+  std::vector<uint32_t> load, one, ext;
   for (const QrArgs& x : a) {
     load.push_back((uint32_t)(((x.d + 31) / 32) * ((x.n + 1 + 31) / 32)));
+    ext.push_back((uint32_t)(((x.n + 31) / 32) * ((x.n + 31) / 32)));
     one.push_back(1u);
     j.maxn = x.n > j.maxn ? x.n : j.maxn;
   }
   j.all = t.add(a.data(), a.size());
   j.mload = t.map(load, &j.nload);
+  j.mextract = t.map(ext, &j.nextract);
   uint32_t tmp = 0;
   j.mone = t.map(one, &tmp);
-  for (int cfg = 0; cfg < 5; ++cfg) {
+  for (int key = 0; key < 10; ++key) {
+    const int cfg = key / 2, cb = 1 + key % 2;
     std::vector<QrArgs> sub;
     std::vector<uint32_t> cone, ctr;
     int64_t maxn = 0;
     for (const QrArgs& x : a) {
-      if (qr_cfg(x.d) != cfg) continue;
+      if (qr_cfg(x.d) != cfg || trail_cb(x.n) != cb) continue;
       sub.push_back(x);
       cone.push_back(1u);
-      ctr.push_back((uint32_t)((x.n + kTrailCB - 1) / kTrailCB));
+      ctr.push_back((uint32_t)((x.n + cb - 1) / cb));
       maxn = x.n > maxn ? x.n : maxn;
     }
     if (sub.empty()) continue;
     QrJob::Cls c;
     c.cfg = cfg;
+    c.cb = cb;
     c.args = t.add(sub.data(), sub.size());
     c.mone = t.map(cone, &tmp);
     c.mtrail = t.map(ctr, &c.ntrail);
@@ -432,13 +478,16 @@ sns_status launch_qr_job(const QrJob& j, hipStream_t st) {
                j.mload);
   for (const QrJob::Cls& c : j.cls) {
     switch (c.cfg) {
-      case 0: run_panels<1, 16>(c, st); break;
-      case 1: run_panels<2, 16>(c, st); break;
-      case 2: run_panels<4, 16>(c, st); break;
-      case 3: run_panels<8, 8>(c, st); break;
-      default: run_panels<16, 4>(c, st); break;
+      // panel configurations: rows per thread, panel width, threads (d <= NT * MAXR)
+      case 0: run_panels_cb<1, 16, 512>(c, st); break;
+      case 1: run_panels_cb<2, 16, 512>(c, st); break;
+      case 2: run_panels_cb<4, 16, 512>(c, st); break;
+      case 3: run_panels_cb<8, 8, 512>(c, st); break;
+      default: run_panels_cb<16, 4, 512>(c, st); break;
     }
   }
+  SNS_LAUNCH("qr_extract", k_qr_extract, dim3(grid_for(j.nextract)), dim3(32, 8), 0, st, j.all,
+             j.mextract);
   const size_t lds = ((size_t)j.maxn + 4096 + 16) * sizeof(double);
   SNS_LAUNCH("qr_finish", k_qr_finish, dim3(grid_for((uint32_t)j.count)), dim3(1024), lds, st,
              j.all, j.mone);
