@@ -110,8 +110,14 @@ __device__ __forceinline__ void panel_step(double (&P)[MAXR][NB], int t, int64_t
   // T[0:K, K] = -tau_K T[0:K, 0:K] (V[:, 0:K]^T v_K), with
   // V[:, a]^T v_K = piv[a] + scale Y_a; T[K, K] = tau_K
   if (t < K) {
+    // all K loads issued together (K is a compile-time bound; b < t adds zero)
     double s = 0.0;
-    for (int b = t; b < K; ++b) s += Ts[b * NB + t] * (piv[b] + scale * tot[b]);
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+      const double tb = Ts[b * NB + t];
+      const double yb = piv[b] + scale * tot[b];
+      s += b >= t ? tb * yb : 0.0;
+    }
     Ts[K * NB + t] = -tk * s;
   }
   if (t == 0) {
