@@ -8,10 +8,10 @@
 // rounded to bfloat16 directly from the double's bits (ties to even).
 //
 // The product is a split-K GEMM on the matrix cores: G is generated per
-// K-step into LDS (one Philox call per thread), A is converted to bf16 into
-// LDS, and each work-group accumulates its 128 x 256 tile of SA over a chunk
-// of rows in fp32; a second kernel adds the chunks in a fixed order and
-// applies d^{-1/2}.
+// K-step into LDS (one Philox call per generator thread), A is converted to
+// bf16 into LDS, and each work-group accumulates its 128 x 512 tile of SA
+// over a chunk of rows in fp32; a second kernel adds the chunks in a fixed
+// order and applies d^{-1/2}.
 #include <math.h>
 #include <mutex>
 #include <string.h>
@@ -70,11 +70,15 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-// Tile of one work-group: 128 sketch rows x 256 columns of SA, fed by K-steps
-// of 32 rows of A.  Four waves: wave (wr, wc) owns rows [64 wr, 64 wr + 64)
+// Tile of one work-group: 128 sketch rows x 512 columns of SA, fed by K-steps
+// of 32 rows of A.  Eight waves: wave (wr, wc) owns rows [64 wr, 64 wr + 64)
 // and columns [128 wc, 128 wc + 128) as 2 x 4 tiles of 32 x 32 computed with
-// v_mfma_f32_32x32x16_bf16 (two k-substeps of 16 per K-step).
-constexpr int kTM = 128, kTN = 256, kKS = 32, kThreads = 256;
+// v_mfma_f32_32x32x16_bf16 (two k-substeps of 16 per K-step).  Every thread
+// streams its share of the next 32 x 512 tile of A while the products run;
+// waves 0-3 also generate the next K-step's G tile (one Philox call per
+// thread).  One G tile serves all 512 columns, so the generator work per flop
+// is half that of a 256-column tile.
+constexpr int kTM = 128, kTN = 512, kKS = 32, kThreads = 512;
 constexpr int kPad = 40;  // LDS row stride in bf16: 32 values + 8 (keeps 16-byte reads conflict free)
 
 struct GaussTable {
@@ -90,30 +94,38 @@ __device__ __forceinline__ __bf16 bits_to_bf16(unsigned short u) {
 // partB[kc][k] = sum G[k, i] bf16(b[i]) (fp32 on the vector units).
 // G[k, i] = T[q], q = byte (i & 15) of Philox4x32-10 at counter
 // (i >> 4, 0, k, 1) (high counter word: i >> 36), key = seed.
-__global__ __launch_bounds__(kThreads, 2) void k_gauss_sketch(
+__global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
     const float* __restrict__ A, int64_t ld, int64_t m, int n, const float* __restrict__ b,
-    uint64_t seed, int d, GaussTable table, int64_t ksteps, int vec_ok, float* __restrict__ partA,
-    float* __restrict__ partB) {
+    uint64_t seed, int d, GaussTable table, int64_t ksteps, int vec_ok, int mt, int nt,
+    float* __restrict__ partA, float* __restrict__ partB) {
   __shared__ unsigned short tbl[256];
   __shared__ __attribute__((aligned(16))) unsigned short Gbuf[2][kTM * kPad];
   __shared__ __attribute__((aligned(16))) unsigned short Bbuf[2][kTN * kPad];
   __shared__ float sbred[2][kTM];
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int k0 = blockIdx.x * kTM, j0 = blockIdx.y * kTN, kc = blockIdx.z, S = gridDim.z;
+  const int wr = wave >> 2, wc = wave & 3;
+  // Work-groups are handed to the 8 XCDs in turn; renumber them so that the
+  // mt sketch-row tiles that read the same rows and columns of A run on one
+  // XCD and share its L2.
+  const int nwg = gridDim.x;
+  const int h = blockIdx.x;
+  const int L = (nwg % 8 == 0) ? (h % 8) * (nwg / 8) + h / 8 : h;
+  const int bx = L % mt, by = (L / mt) % nt, kc = L / (mt * nt), S = nwg / (mt * nt);
+  const int k0 = bx * kTM, j0 = by * kTN;
   const int64_t s0 = ksteps * kc / S, s1 = ksteps * (kc + 1) / S;
   if (t < 128) {
     tbl[2 * t] = (unsigned short)(table.w[t] & 0xFFFFu);
     tbl[2 * t + 1] = (unsigned short)(table.w[t] >> 16);
   }
-  // generator role: sketch row r, half h (16 consecutive rows of A)
-  const int gr = t & 127, gh = t >> 7;
+  const bool gen = t < 256;  // waves 0-3 also generate G
+  // generator role: sketch row gr, half gh (16 consecutive rows of A)
+  const int gr = t & 127, gh = (t >> 7) & 1;
   const int gk = k0 + gr;
-  const bool do_b = b != nullptr && blockIdx.y == 0;
+  const bool do_b = b != nullptr && by == 0;
   float sb = 0.f;
-  // A-loading role: 4 columns (4 ac .. 4 ac + 3), 8 rows (8 ar .. 8 ar + 7)
-  const int ac = t & 63, ar = t >> 6;
+  // A-loading role (every thread): 4 columns (4 ac .. 4 ac + 3), 8 rows (8 ar .. 8 ar + 7)
+  const int ac = t & 127, ar = t >> 7;
   const int aj = j0 + 4 * ac;
 
   f32x16 acc[2][4];
@@ -125,16 +137,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_gauss_sketch(
       for (int q = 0; q < 16; ++q) acc[rt][ct][q] = 0.f;
 
   float av[8][4];
+  // this thread's 4 columns are all inside A (vector loads) when vec_ok
+  const bool cols_in = vec_ok && aj + 3 < n;
   auto load_A = [&](int64_t st) {
+    const int64_t i0 = st * kKS + 8 * ar;
+    const float* p = A + i0 * ld + aj;  // one 64-bit product per step; rows by pointer steps
+    if (cols_in) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t i = st * kKS + 8 * ar + e;
-      if (i < m && vec_ok && aj + 3 < n) {
-        const float4 x = *reinterpret_cast<const float4*>(A + i * ld + aj);
+      for (int e = 0; e < 8; ++e) {
+        float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i0 + e < m) x = *reinterpret_cast<const float4*>(p);
         av[e][0] = x.x; av[e][1] = x.y; av[e][2] = x.z; av[e][3] = x.w;
-      } else {
+        p += ld;
+      }
+    } else {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) av[e][c] = (i < m && aj + c < n) ? A[i * ld + aj + c] : 0.f;
+      for (int e = 0; e < 8; ++e) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) av[e][c] = (i0 + e < m && aj + c < n) ? p[c] : 0.f;
+        p += ld;
       }
     }
   };
@@ -162,10 +183,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_gauss_sketch(
       }
       if (do_b) {
         const int64_t ib = (int64_t)jb * 16;
+        const float* bp = b + ib;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const int64_t i = ib + e;
-          const float bv = i < m ? (float)(__bf16)b[i] : 0.f;
+          const float bv = ib + e < m ? (float)(__bf16)bp[e] : 0.f;
           sb = fmaf((float)(e < 8 ? lo[e] : hi[e - 8]), bv, sb);
         }
       }
@@ -200,16 +221,16 @@ __global__ __launch_bounds__(kThreads, 2) void k_gauss_sketch(
   __syncthreads();  // table ready
   if (s0 < s1) {
     load_A(s0);
-    gen_G(s0, 0);
+    if (gen) gen_G(s0, 0);
     store_A(0);
     __syncthreads();
     for (int64_t st = s0; st < s1; ++st) {
       const int cur = (int)((st - s0) & 1), nxt = cur ^ 1;
       const bool more = st + 1 < s1;
-      if (more) load_A(st + 1);
+      if (more) load_A(st + 1);  // in flight during the products
       mfma(cur);
       if (more) {
-        gen_G(st + 1, nxt);
+        if (gen) gen_G(st + 1, nxt);
         store_A(nxt);
       }
       __syncthreads();
@@ -230,7 +251,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gauss_sketch(
       }
     }
   if (do_b) {
-    sbred[gh][gr] = sb;
+    if (gen) sbred[gh][gr] = sb;
     __syncthreads();
     if (t < kTM && k0 + t < d) partB[(size_t)kc * d + k0 + t] = sbred[0][t] + sbred[1][t];
   }
@@ -266,7 +287,7 @@ GaussPlan make_gauss_plan(const sns_matrix& A, uint32_t d) {
   g.nt = (int)((A.n + kTN - 1) / kTN);
   g.ksteps = (A.m + kKS - 1) / kKS;
   const int64_t tiles = (int64_t)g.mt * g.nt;
-  int64_t S = (512 + tiles - 1) / tiles;        // about two work-groups per CU
+  int64_t S = (256 + tiles - 1) / tiles;        // one work-group per CU (LDS-limited)
   const int64_t maxS = g.ksteps / 8 > 0 ? g.ksteps / 8 : 1;  // >= 8 K-steps per chunk
   if (S > maxS) S = maxS;
   if (S > 256) S = 256;
@@ -293,9 +314,10 @@ sns_status launch_gauss_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, c
   const uint16_t* T = gauss_table_host();
   for (int e = 0; e < 128; ++e) tab.w[e] = (uint32_t)T[2 * e] | ((uint32_t)T[2 * e + 1] << 16);
   const int vec_ok = ((uintptr_t)A.values % 16 == 0) && (A.ld % 4 == 0);
-  SNS_LAUNCH("gauss_mfma", k_gauss_sketch, dim3(g.mt, g.nt, g.S), dim3(kThreads), 0, st,
+  SNS_LAUNCH("gauss_mfma", k_gauss_sketch, dim3(g.mt * g.nt * g.S), dim3(kThreads), 0, st,
              static_cast<const float*>(A.values), A.ld, A.m, (int)A.n,
-             static_cast<const float*>(b), seed, (int)d, tab, g.ksteps, vec_ok, partA, partB);
+             static_cast<const float*>(b), seed, (int)d, tab, g.ksteps, vec_ok, g.mt, g.nt, partA,
+             partB);
   const int64_t dn = (int64_t)d * A.n;
   int64_t blocks = (dn + d + 255) / 256;
   if (blocks > 8192) blocks = 8192;
