@@ -102,6 +102,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
   __shared__ __attribute__((aligned(16))) unsigned short Gbuf[2][kTM * kPad];
   __shared__ __attribute__((aligned(16))) unsigned short Bbuf[2][kTN * kPad];
   __shared__ float sbred[2][kTM];
+  __shared__ __attribute__((aligned(16))) float bsh[2][kKS];  // bf16(b) of the staged K-steps
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wr = wave >> 2, wc = wave & 3;
@@ -137,6 +138,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
       for (int q = 0; q < 16; ++q) acc[rt][ct][q] = 0.f;
 
   float av[8][4];
+  float bq[4];  // threads 0-7: b[32 st + 4 t .. + 3] of the K-step being staged
+  const bool b_loader = do_b && t < kKS / 4;
   // this thread's 4 columns are all inside A (vector loads) when vec_ok
   const bool cols_in = vec_ok && aj + 3 < n;
   auto load_A = [&](int64_t st) {
@@ -159,7 +162,16 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
       }
     }
   };
+  auto load_b = [&](int64_t st) {
+    const int64_t i0 = st * kKS + 4 * t;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bq[c] = i0 + c < m ? b[i0 + c] : 0.f;
+  };
   auto store_A = [&](int buf) {
+    if (b_loader) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bsh[buf][4 * t + c] = (float)(__bf16)bq[c];
+    }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       bf16x8 v;
@@ -181,21 +193,26 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
         if (e < 8) lo[e] = bits_to_bf16(g);
         else hi[e - 8] = bits_to_bf16(g);
       }
-      if (do_b) {
-        const int64_t ib = (int64_t)jb * 16;
-        const float* bp = b + ib;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const float bv = ib + e < m ? (float)(__bf16)bp[e] : 0.f;
-          sb = fmaf((float)(e < 8 ? lo[e] : hi[e - 8]), bv, sb);
-        }
-      }
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) { lo[e] = (__bf16)0.f; hi[e] = (__bf16)0.f; }
     }
     *reinterpret_cast<bf16x8*>(&Gbuf[buf][gr * kPad + 16 * gh]) = lo;
     *reinterpret_cast<bf16x8*>(&Gbuf[buf][gr * kPad + 16 * gh + 8]) = hi;
+  };
+  // Sb partial of this K-step: generator row gr, its 16 rows of half gh, in order
+  auto sketch_b = [&](int buf) {
+    const bf16x8 lo = *reinterpret_cast<const bf16x8*>(&Gbuf[buf][gr * kPad + 16 * gh]);
+    const bf16x8 hi = *reinterpret_cast<const bf16x8*>(&Gbuf[buf][gr * kPad + 16 * gh + 8]);
+    const float4* bp = reinterpret_cast<const float4*>(&bsh[buf][16 * gh]);
+    float bv[16];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float4 x = bp[c];
+      bv[4 * c] = x.x; bv[4 * c + 1] = x.y; bv[4 * c + 2] = x.z; bv[4 * c + 3] = x.w;
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sb = fmaf((float)(e < 8 ? lo[e] : hi[e - 8]), bv[e], sb);
   };
   auto mfma = [&](int buf) {
 #pragma unroll
@@ -221,14 +238,19 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
   __syncthreads();  // table ready
   if (s0 < s1) {
     load_A(s0);
+    if (b_loader) load_b(s0);
     if (gen) gen_G(s0, 0);
     store_A(0);
     __syncthreads();
     for (int64_t st = s0; st < s1; ++st) {
       const int cur = (int)((st - s0) & 1), nxt = cur ^ 1;
       const bool more = st + 1 < s1;
-      if (more) load_A(st + 1);  // in flight during the products
+      if (more) {  // in flight during the products
+        load_A(st + 1);
+        if (b_loader) load_b(st + 1);
+      }
       mfma(cur);
+      if (do_b && gen && gk < d) sketch_b(cur);
       if (more) {
         if (gen) gen_G(st + 1, nxt);
         store_A(nxt);
