@@ -16,6 +16,8 @@
 #include <mutex>
 #include <string.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -79,11 +81,26 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 // thread).  One G tile serves all 512 columns, so the generator work per flop
 // is half that of a 256-column tile.
 constexpr int kTM = 128, kTN = 512, kKS = 32, kThreads = 512;
+// LDS stages: the tile of K-step st is staged during K-step st - 2, so a wave
+// can read the next K-step's first fragments before the barrier that closes
+// the current one.
+constexpr int kStages = 3;
 constexpr int kPad = 40;  // LDS row stride in bf16: 32 values + 8 (keeps 16-byte reads conflict free)
 
 struct GaussTable {
   uint32_t w[128];  // T[2e] in the low half, T[2e + 1] in the high half
 };
+
+// A tile in LDS: one row of kPad bf16 per column of A, holding its 32 K-step
+// values as four 16-byte chunks.  Chunk q of row r sits at slot q ^ aswz(r),
+// so that the 16-byte stores of one wave (rows 4 l + c, l = lane) spread over
+// all banks while the fragment reads (32 consecutive rows, one chunk) stay
+// conflict free.
+#ifndef SNS_GAUSS_SWZ64
+__device__ __forceinline__ int aswz(int r) { return ((r >> 4) & 1) | (((r >> 3) & 1) << 1); }
+#else
+__device__ __forceinline__ int aswz(int r) { return ((r >> 5) & 1) | (((r >> 4) & 1) << 1); }
+#endif
 
 __device__ __forceinline__ __bf16 bits_to_bf16(unsigned short u) {
   return __builtin_bit_cast(__bf16, u);
@@ -99,10 +116,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
     uint64_t seed, int d, GaussTable table, int64_t ksteps, int vec_ok, int mt, int nt,
     float* __restrict__ partA, float* __restrict__ partB) {
   __shared__ unsigned short tbl[256];
-  __shared__ __attribute__((aligned(16))) unsigned short Gbuf[2][kTM * kPad];
-  __shared__ __attribute__((aligned(16))) unsigned short Bbuf[2][kTN * kPad];
+  __shared__ __attribute__((aligned(16))) unsigned short Gbuf[kStages][kTM * kPad];
+  __shared__ __attribute__((aligned(16))) unsigned short Bbuf[kStages][kTN * kPad];
   __shared__ float sbred[2][kTM];
-  __shared__ __attribute__((aligned(16))) float bsh[2][kKS];  // bf16(b) of the staged K-steps
+  __shared__ __attribute__((aligned(16))) float bsh[kStages][kKS];  // b of the staged K-steps (rounded to bf16 when read)
 
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wr = wave >> 2, wc = wave & 3;
@@ -167,32 +184,39 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
 #pragma unroll
     for (int c = 0; c < 4; ++c) bq[c] = i0 + c < m ? b[i0 + c] : 0.f;
   };
-  auto store_A = [&](int buf) {
-    if (b_loader) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) bsh[buf][4 * t + c] = (float)(__bf16)bq[c];
-    }
+  auto store_tile = [&](int buf) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       bf16x8 v;
 #pragma unroll
       for (int e = 0; e < 8; ++e) v[e] = (__bf16)av[e][c];
-      *reinterpret_cast<bf16x8*>(&Bbuf[buf][(4 * ac + c) * kPad + 8 * ar]) = v;
+      *reinterpret_cast<bf16x8*>(&Bbuf[buf][(4 * ac + c) * kPad + 8 * (ar ^ aswz(4 * ac + c))]) = v;
+    }
+  };  auto store_A = [&](int buf) {
+    if (b_loader) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bsh[buf][4 * t + c] = bq[c];
+    }
+    store_tile(buf);
+  };
+
+  // G[gk, 16 jb .. 16 jb + 15] for the K-step st: one Philox call, 16 table lookups
+  auto make_G = [&](int64_t st, bf16x8& lo, bf16x8& hi) {
+    const uint64_t jb = (uint64_t)(st * kKS) / 16 + gh;  // 16-row block of A
+    const U4 w = philox4x32_10(U4{(uint32_t)jb, (uint32_t)(jb >> 32), (uint32_t)gk, 1u},
+                               (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const unsigned short g = tbl[(wv[e >> 2] >> (8 * (e & 3))) & 0xFFu];
+      if (e < 8) lo[e] = bits_to_bf16(g);
+      else hi[e - 8] = bits_to_bf16(g);
     }
   };
   auto gen_G = [&](int64_t st, int buf) {
-    const uint64_t jb = (uint64_t)(st * kKS) / 16 + gh;  // 16-row block of A
     bf16x8 lo, hi;
     if (gk < d) {
-      const U4 w = philox4x32_10(U4{(uint32_t)jb, (uint32_t)(jb >> 32), (uint32_t)gk, 1u},
-                                 (uint32_t)seed, (uint32_t)(seed >> 32));
-      const uint32_t wv[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const unsigned short g = tbl[(wv[e >> 2] >> (8 * (e & 3))) & 0xFFu];
-        if (e < 8) lo[e] = bits_to_bf16(g);
-        else hi[e - 8] = bits_to_bf16(g);
-      }
+      make_G(st, lo, hi);
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) { lo[e] = (__bf16)0.f; hi[e] = (__bf16)0.f; }
@@ -212,6 +236,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
       bv[4 * c] = x.x; bv[4 * c + 1] = x.y; bv[4 * c + 2] = x.z; bv[4 * c + 3] = x.w;
     }
 #pragma unroll
+    for (int e = 0; e < 16; ++e) bv[e] = (float)(__bf16)bv[e];
+#pragma unroll
     for (int e = 0; e < 16; ++e) sb = fmaf((float)(e < 8 ? lo[e] : hi[e - 8]), bv[e], sb);
   };
   auto mfma = [&](int buf) {
@@ -224,9 +250,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
         ao[rt] = *reinterpret_cast<const bf16x8*>(
             &Gbuf[buf][(wr * 64 + rt * 32 + (lane & 31)) * kPad + kofs]);
 #pragma unroll
-      for (int ct = 0; ct < 4; ++ct)
+      for (int ct = 0; ct < 4; ++ct) {
+        const int r = wc * 128 + ct * 32 + (lane & 31);
         bo[ct] = *reinterpret_cast<const bf16x8*>(
-            &Bbuf[buf][(wc * 128 + ct * 32 + (lane & 31)) * kPad + kofs]);
+            &Bbuf[buf][r * kPad + 8 * ((2 * ks + (lane >> 5)) ^ aswz(r))]);
+      }
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
@@ -235,27 +263,173 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
     }
   };
 
+  // fragments of one K-substep from stage slot sl: G rows (f < 2), A columns (f >= 2)
+  auto frag = [&](int sl, int ks, int f, bf16x8* ao, bf16x8* bo) {
+    if (f < 2) {
+      ao[f] = *reinterpret_cast<const bf16x8*>(
+          &Gbuf[sl][(wr * 64 + f * 32 + (lane & 31)) * kPad + 16 * ks + 8 * (lane >> 5)]);
+    } else {
+      const int r = wc * 128 + (f - 2) * 32 + (lane & 31);
+      bo[f - 2] = *reinterpret_cast<const bf16x8*>(
+          &Bbuf[sl][r * kPad + 8 * ((2 * ks + (lane >> 5)) ^ aswz(r))]);
+    }
+  };
+
   __syncthreads();  // table ready
   if (s0 < s1) {
+    // prologue: stage the first two K-steps
     load_A(s0);
     if (b_loader) load_b(s0);
     if (gen) gen_G(s0, 0);
     store_A(0);
+    if (s0 + 1 < s1) {
+      load_A(s0 + 1);
+      if (b_loader) load_b(s0 + 1);
+      if (gen) gen_G(s0 + 1, 1);
+      store_A(1);
+    }
     __syncthreads();
-    for (int64_t st = s0; st < s1; ++st) {
-      const int cur = (int)((st - s0) & 1), nxt = cur ^ 1;
-      const bool more = st + 1 < s1;
+    // Straight-line K-steps: the K-step staged two ahead lies wholly inside A
+    // (all 32 rows, this tile's 512 columns by vector loads) and every
+    // generator row is a sketch row.  Each wave role runs its own loop with no
+    // branch in the body, so the products can be interleaved with the loads,
+    // the generator and the LDS stores; both loops meet the same barriers.
+    const bool wg_fast = vec_ok && j0 + kTN <= n && k0 + kTM <= d;
+    const int64_t sfull = m / kKS;  // K-steps [0, sfull) are full
+    int64_t sf_end = (s1 < sfull ? s1 : sfull) - 2;
+    if (!wg_fast || sf_end < s0) sf_end = s0;
+    int cur = 0;
+    bf16x8 f0a[2], f0b[4];  // first-substep fragments of the current K-step
+    auto fast_step = [&](auto genc, auto dobc, int64_t st) {
+      constexpr bool GEN = decltype(genc)::value, DOB = decltype(dobc)::value;
+      const int n1 = cur == kStages - 1 ? 0 : cur + 1, n2 = n1 == kStages - 1 ? 0 : n1 + 1;
+      const int64_t sn = st + 2;  // the K-step staged now
+      float bn[4];
+      if constexpr (DOB) {  // product lanes stage 4 values of b each (8 distinct per wave)
+        const float* bp = b + sn * kKS + 4 * (lane & 7);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) bn[c] = bp[c];
+      }
+      const float* p = A + (sn * kKS + 8 * ar) * ld + aj;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float4 x = *reinterpret_cast<const float4*>(p);
+        av[e][0] = x.x; av[e][1] = x.y; av[e][2] = x.z; av[e][3] = x.w;
+        p += ld;
+      }
+      __builtin_amdgcn_sched_barrier(0);  // the global loads go out first
+      bf16x8 f1a[2], f1b[4];
+      if constexpr (!GEN) {
+        // Product waves: the second substep's fragments and (with b) this
+        // K-step's Sb terms in the shadow of the products, in a fixed order.
+        bf16x8 glo, ghi;
+        float bv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int ks = q >> 3, rt = (q >> 2) & 1, ct = q & 3;
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ks ? f1a[rt] : f0a[rt],
+                                                                ks ? f1b[ct] : f0b[ct],
+                                                                acc[rt][ct], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if (q < 6) frag(cur, 1, q, f1a, f1b);
+          if constexpr (DOB) {
+            if (q == 6) {
+              glo = *reinterpret_cast<const bf16x8*>(&Gbuf[cur][gr * kPad + 16 * gh]);
+              ghi = *reinterpret_cast<const bf16x8*>(&Gbuf[cur][gr * kPad + 16 * gh + 8]);
+              const float4* bp4 = reinterpret_cast<const float4*>(&bsh[cur][16 * gh]);
+#pragma unroll
+              for (int c = 0; c < 4; ++c) {
+                const float4 x = bp4[c];
+                bv[4 * c] = x.x; bv[4 * c + 1] = x.y; bv[4 * c + 2] = x.z; bv[4 * c + 3] = x.w;
+              }
+#pragma unroll
+              for (int e = 0; e < 16; ++e) bv[e] = (float)(__bf16)bv[e];
+            } else if (q == 10 || q == 11) {
+#pragma unroll
+              for (int e = 8 * (q - 10); e < 8 * (q - 9); ++e)
+                sb = fmaf((float)(e < 8 ? glo[e] : ghi[e - 8]), bv[e], sb);
+            } else if (q == 15) {
+              *reinterpret_cast<float4*>(&bsh[n2][4 * (lane & 7)]) =
+                  make_float4(bn[0], bn[1], bn[2], bn[3]);
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      } else {
+        // The generator's work for the K-step staged now runs in the shadow
+        // of the 16 products, one slice after each product (the order is fixed
+        // with scheduling fences): the second substep's fragment reads, the
+        // ten Philox rounds, the 16 table lookups, then the G row's stores.
+        const uint64_t jb = (uint64_t)(sn * kKS) / 16 + gh;
+        U4 c = U4{(uint32_t)jb, (uint32_t)(jb >> 32), (uint32_t)gk, 1u};
+        bf16x8 lo, hi;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int ks = q >> 3, rt = (q >> 2) & 1, ct = q & 3;
+          acc[rt][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ks ? f1a[rt] : f0a[rt],
+                                                                ks ? f1b[ct] : f0b[ct],
+                                                                acc[rt][ct], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          if (q < 6) frag(cur, 1, q, f1a, f1b);
+          if (q < 10) {  // Philox4x32-10 round q (key bumped q times)
+            const uint32_t k0 = (uint32_t)seed + (uint32_t)q * 0x9E3779B9u;
+            const uint32_t k1 = (uint32_t)(seed >> 32) + (uint32_t)q * 0xBB67AE85u;
+            const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+            c = U4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                   (uint32_t)p0};
+          } else if (q == 10) {
+            const uint32_t wv[2] = {c.x, c.y};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) lo[e] = bits_to_bf16(tbl[(wv[e >> 2] >> (8 * (e & 3))) & 0xFFu]);
+          } else if (q == 11) {
+            const uint32_t wv[2] = {c.z, c.w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) hi[e] = bits_to_bf16(tbl[(wv[e >> 2] >> (8 * (e & 3))) & 0xFFu]);
+          } else if (q == 13) {
+            *reinterpret_cast<bf16x8*>(&Gbuf[n2][gr * kPad + 16 * gh]) = lo;
+            *reinterpret_cast<bf16x8*>(&Gbuf[n2][gr * kPad + 16 * gh + 8]) = hi;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      store_tile(n2);
+      // K-step st + 1 was staged before the last barrier: read its first
+      // fragments now, so the products can start right after this barrier.
+#pragma unroll
+      for (int f = 0; f < 6; ++f) frag(n1, 0, f, f0a, f0b);
+      __syncthreads();
+      cur = n1;
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    int64_t st = s0;
+    if (sf_end > s0) {
+#pragma unroll
+      for (int f = 0; f < 6; ++f) frag(cur, 0, f, f0a, f0b);
+      if (gen) {
+        for (; st < sf_end; ++st) fast_step(T_{}, F_{}, st);
+      } else {
+        if (do_b)
+          for (; st < sf_end; ++st) fast_step(F_{}, T_{}, st);
+        else
+          for (; st < sf_end; ++st) fast_step(F_{}, F_{}, st);
+      }
+    }
+    for (; st < s1; ++st) {
+      const int n1 = cur == kStages - 1 ? 0 : cur + 1, n2 = n1 == kStages - 1 ? 0 : n1 + 1;
+      const bool more = st + 2 < s1;
       if (more) {  // in flight during the products
-        load_A(st + 1);
-        if (b_loader) load_b(st + 1);
+        load_A(st + 2);
+        if (b_loader) load_b(st + 2);
       }
       mfma(cur);
-      if (do_b && gen && gk < d) sketch_b(cur);
+      if (do_b && !gen && gk < d) sketch_b(cur);
       if (more) {
-        if (gen) gen_G(st + 1, nxt);
-        store_A(nxt);
+        if (gen) gen_G(st + 2, n2);
+        store_A(n2);
       }
       __syncthreads();
+      cur = n1;
     }
   }
   // epilogue: accumulator element q of lane l in a 32 x 32 tile is
@@ -273,7 +447,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_gauss_sketch(
       }
     }
   if (do_b) {
-    if (gen) sbred[gh][gr] = sb;
+    if (!gen) sbred[gh][gr] = sb;
     __syncthreads();
     if (t < kTM && k0 + t < d) partB[(size_t)kc * d + k0 + t] = sbred[0][t] + sbred[1][t];
   }

@@ -26,7 +26,7 @@ def _dev(x, torch):
 
 
 @pytest.mark.parametrize("m,n,d", [(4096, 64, 256), (10000, 100, 200), (3000, 257, 300), (777, 5, 130),
-                                   (50000, 512, 1024)])
+                                   (50000, 512, 1024), (40013, 512, 1000), (20011, 1100, 1160)])
 def test_gaussian_sketch_matches_oracle(gpu_lib, m, n, d):
     import torch
     rng = np.random.default_rng(m + n + d)
