@@ -9,6 +9,11 @@ TEST INFRASTRUCTURE ONLY: nothing in the product path may import this module.
   start from the sketch-and-solve x_0, then run LSQR on A R^{-1} (applied as
   v -> A (R^{-1} v) and u -> R^{-T} (A^T u), never formed) against the
   residual r_0 = b - A x_0, and return x = x_0 + R^{-1} dy.
+* saa_sas: the sketch-and-apply solver named beside it (SAA-SAS): the same
+  start, but the preconditioned matrix Y = A R^{-1} is formed explicitly
+  (column by column from Y R = A) and LSQR runs on Y itself.  In exact
+  arithmetic its iterates are those of SAP-SAS.  `y_dtype` rounds Y to a
+  storage precision before the iterations (float32 for float32 inputs).
 
 Stop rule (reading C-8): with sigma_hat = 1 - sqrt(n / d), the lower edge of
 the Marchenko-Pastur law for the singular values of the preconditioned
@@ -88,6 +93,37 @@ def sap_sas(A, b, kind: str, seed: int, d: int, max_iters: int, rtol: float = 0.
     res = lsqr(lambda v: _matvec(Af, back_substitution(R, v)),
                lambda u: forward_substitution_transposed(R, _rmatvec(Af, u)),
                r0, n, max_iters, stop_ratio=rtol * sigma_hat(n, d))
+    x = base.x0 + back_substitution(R, res.x)
+    return SolveResult(x, base.x0, R, base.c, base.rho, res.iters, base.rank_deficient,
+                       res.rnorm, res.arnorm)
+
+
+def form_y(A, R: np.ndarray) -> np.ndarray:
+    """Y = A R^{-1} for upper-triangular R, one column at a time from Y R = A:
+    Y[:, j] = (A[:, j] - Y[:, :j] R[:j, j]) / R[j, j]."""
+    Af = A.toarray() if sp.issparse(A) else np.asarray(A)
+    Af = Af.astype(np.float64)
+    m, n = Af.shape
+    Y = np.empty((m, n))
+    for j in range(n):
+        Y[:, j] = (Af[:, j] - Y[:, :j] @ R[:j, j]) / R[j, j]
+    return Y
+
+
+def saa_sas(A, b, kind: str, seed: int, d: int, max_iters: int, rtol: float = 0.0,
+            SA=None, Sb=None, y_dtype=None) -> SolveResult:
+    """SAA-SAS; rtol = 0 runs exactly max_iters LSQR iterations."""
+    base = sketch_and_solve(A, b, kind, seed, d, SA, Sb)
+    R = base.R
+    n = R.shape[0]
+    Y = form_y(A, R)
+    if y_dtype is not None:
+        Y = Y.astype(y_dtype).astype(np.float64)
+    Af = A.astype(np.float64) if sp.issparse(A) else np.asarray(A, dtype=np.float64)
+    bf = np.asarray(b, dtype=np.float64)
+    r0 = bf - _matvec(Af, base.x0)
+    res = lsqr(lambda v: Y @ v, lambda u: Y.T @ u, r0, n, max_iters,
+               stop_ratio=rtol * sigma_hat(n, d))
     x = base.x0 + back_substitution(R, res.x)
     return SolveResult(x, base.x0, R, base.c, base.rho, res.iters, base.rank_deficient,
                        res.rnorm, res.arnorm)

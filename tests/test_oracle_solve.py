@@ -9,7 +9,12 @@ LSQR: iterates equal scipy.sparse.linalg.lsqr's for the same iteration count
 and its residual-norm estimates equal the true norms.  SAS: the closed form
 E||b - A x_0||^2 = ||r*||^2 (1 + n / (d - n - 1)) for a Gaussian sketch.
 SAP-SAS: the preconditioned spectrum lies near the Marchenko-Pastur edges and
-the stop rule delivers RE <= 1e-6.  Metrics: (1 + SUB)^2 = 1 + RE^2.
+the stop rule delivers RE <= 1e-6.  SAA-SAS: the explicit Y = A R^{-1}
+equals scipy's triangular solve and satisfies Y R = A; its iterates agree
+with SAP-SAS (the same method in exact arithmetic) and it reaches the same
+target, also with Y stored in float32.  The paper's benchmark generator
+(Sec. 3.1) has the requested singular values and optimal residual norm beta.
+Metrics: (1 + SUB)^2 = 1 + RE^2.
 """
 import math
 
@@ -23,7 +28,7 @@ from oracle import metrics as MT
 from oracle import qr as Q
 from oracle import sketch as S
 from oracle import solve as SV
-from workloads import dense_gaussian, dense_ill_conditioned, dense_scaled_columns
+from workloads import dense_gaussian, dense_ill_conditioned, dense_scaled_columns, paper_benchmark
 
 
 def test_qr_matches_lapack_r_exactly_in_sign():
@@ -170,3 +175,47 @@ def test_sap_sas_exact_recovery_and_fixed_iterations():
     xs = MT.lstsq_exact(p.A, p.b)
     r2 = SV.sap_sas(p.A, p.b, "count", 42, 96, 60, rtol=1e-12)
     assert np.linalg.norm(p.A.astype(np.float64) @ (r2.x - xs)) <= 1e-9 * np.linalg.norm(p.b)
+
+
+def test_form_y_matches_triangular_solve_and_reconstructs_a():
+    p = dense_ill_conditioned(3000, 40, seed=13, cond=1e4)
+    r = SV.sketch_and_solve(p.A, p.b, "count", 42, 160)
+    Y = SV.form_y(p.A, r.R)
+    Af = p.A.astype(np.float64)
+    ref = sla.solve_triangular(r.R, Af.T, trans="T", lower=False).T
+    assert np.linalg.norm(Y - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.linalg.norm(Y @ r.R - Af) <= 1e-13 * np.linalg.norm(Af)
+    # the explicit preconditioned matrix is well conditioned (d = 4n)
+    sv = np.linalg.svd(Y, compute_uv=False)
+    assert sv.max() / sv.min() < 6.0
+
+
+def test_saa_sas_iterates_equal_sap_sas():
+    p = dense_scaled_columns(20000, 32, seed=14)
+    a = SV.sap_sas(p.A, p.b, "count", 42, 128, 8)
+    c = SV.saa_sas(p.A, p.b, "count", 42, 128, 8)
+    assert a.iters == c.iters == 8
+    assert np.linalg.norm(a.x - c.x) <= 1e-10 * np.linalg.norm(a.x)
+    assert abs(a.rnorm - c.rnorm) <= 1e-10 * a.rnorm
+
+
+@pytest.mark.parametrize("y_dtype", [None, np.float32])
+def test_saa_sas_stop_rule_reaches_target(y_dtype):
+    p = dense_ill_conditioned(60000, 48, seed=10)
+    xs = MT.lstsq_exact(p.A, p.b)
+    r = SV.saa_sas(p.A, p.b, "count", 42, 192, 100, rtol=1e-6, y_dtype=y_dtype)
+    m = MT.metrics(p.A, p.b, r.x, xs)
+    assert m["RE"] <= 1e-6
+    assert r.iters < 40
+
+
+def test_paper_benchmark_generator():
+    p = paper_benchmark(3000, 60, seed=15, cond=1e10, beta=1e-10)
+    sv = np.linalg.svd(p.A, compute_uv=False)
+    sigma = np.logspace(0.0, -10.0, 60)
+    # large singular values to relative rounding; the small ones to ||A|| u
+    assert np.all(np.abs(sv - sigma) <= 1e-12 * sigma + 1e-14)
+    # x is the least-squares solution and the optimal residual norm is beta
+    r = p.b - p.A @ p.x_true
+    assert abs(np.linalg.norm(r) - 1e-10) <= 1e-12
+    assert np.linalg.norm(p.A.T @ r) <= 1e-14 * np.linalg.norm(r) * 10 + 1e-16
