@@ -100,8 +100,9 @@ typedef struct {
 } sns_sketch;
 
 typedef struct {
-  int refine;      /* 0: plain sketch-and-solve; 1: SAP-SAS (LSQR on A R^{-1}) */
-  int max_iters;   /* LSQR iteration cap (refine = 1) */
+  int refine;      /* 0: plain sketch-and-solve; 1: SAP-SAS (LSQR on A R^{-1} applied
+                      implicitly); 2: SAA-SAS (Y = A R^{-1} formed, LSQR on Y; sns_lstsq only) */
+  int max_iters;   /* LSQR iteration cap (refine = 1 or 2) */
   double rtol;     /* stop when ||Abar^T r|| / ||r|| <= rtol (1 - sqrt(n/d));
                       rtol = 0 runs exactly max_iters iterations */
   int accum_fp64;  /* 1: accumulate the CountSketch in fp64 (fp32 inputs) */
@@ -178,10 +179,16 @@ sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
  * b: device, m entries of A's dtype.  x: device fp64[n].
  * info: HOST pointer (pinned memory recommended) or NULL; written on the
  * stream, valid after synchronising it.
+ * With opts->refine = 2, the SAA-SAS variant named beside it in Sec. 2.1:
+ * Y = A R^{-1} is formed once (fp64 products, stored in A's dtype inside the
+ * workspace, m x n) and LSQR runs on Y from the same r0; x = x0 + R^{-1} dy.
+ * In exact arithmetic both variants give the same iterates; SAA costs one
+ * extra pass that reads A and writes Y plus about m n^2 multiply-adds, and
+ * its workspace holds Y.
  * A may be CSR with refine = 0 (plain sketch-and-solve); refinement streams
  * dense rows and returns SNS_ERR_DTYPE for CSR.
- * Errors: as sns_sketch_apply, plus SNS_ERR_INVALID_ARG for max_iters < 0 or
- * rtol < 0. */
+ * Errors: as sns_sketch_apply, plus SNS_ERR_INVALID_ARG for refine outside
+ * 0..2, max_iters < 0 or rtol < 0. */
 sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, double* x,
                      const sns_solve_opts* opts, void* workspace, size_t ws_bytes,
                      sns_info* info, void* stream);
@@ -192,7 +199,7 @@ typedef struct {
   sns_matrix A;         /* dense row-major */
   const void* b;        /* device, m entries of A's dtype */
   double* x;            /* device fp64[n], the answer */
-  sns_solve_opts opts;  /* as for sns_lstsq */
+  sns_solve_opts opts;  /* as for sns_lstsq, refine 0 or 1 (2: SNS_ERR_INVALID_ARG) */
 } sns_problem;
 
 /* Workspace bytes sns_lstsq_batched needs for these problems. */

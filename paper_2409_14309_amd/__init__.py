@@ -55,13 +55,18 @@ def sketch(A, b=None, kind: str = "count", d: int = None, seed: int = 42, accum_
     return SA, Sb
 
 
-def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine: bool = False,
+REFINE = {False: 0, True: 1, 0: 0, 1: 1, 2: 2, "sas": 0, "sap": 1, "saa": 2}
+
+
+def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine=False,
           max_iters: int = 100, rtol: float = 1e-6, accum_fp64: bool = False, stream=None):
-    """x (float64 device tensor) and Info for min ||A x - b||."""
+    """x (float64 device tensor) and Info for min ||A x - b||.  refine: False /
+    "sas" (plain sketch-and-solve), True / "sap" (SAP-SAS) or "saa" (SAA-SAS)."""
     import torch
     sk = sketch_desc(kind, d, seed)
     M = _describe(A)
-    o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0, int(accum_fp64))
+    r = REFINE[refine]
+    o = opts(r, max_iters if r else 0, rtol if r else 0.0, int(accum_fp64))
     ws = _workspace(sns_lstsq_workspace_size(sk, M, o), A.device)
     x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
     info = Info()

@@ -306,19 +306,34 @@ struct LsqrArgs {
   double* x;
   sns_info* info;
   double sighat, stop;
+  const void* Y;  // SAA-SAS: explicit A R^{-1} (A's dtype, row stride ldy); null for SAP-SAS
+  int64_t ldy;
 };
 // SAP-SAS refinement of one problem: LSQR on A R^{-1} from r0 = b - A x0.  R
 // is the n x n column-major factor in q.R; x0 in q.xw.  Writes x (fp64 n) and
 // updates info (iters, rel_resid_est, status).
 LsqrArgs lsqr_args(const sns_matrix& A, const void* b, const LsqrPlan& p, const LsqrBufs& l,
                    const QrBufs& q, int d, int max_iters, double rtol, double* x,
-                   sns_info* info);
+                   sns_info* info, const void* Y = nullptr, int64_t ldy = 0);
+// SAA-SAS: Y = A X (X = R^{-1}, row-major fp64) formed once after X.
+struct SaaJob {
+  const void* A = nullptr;
+  int64_t ld = 0, m = 0;
+  int n = 0;
+  const double* X = nullptr;
+  void* Y = nullptr;
+  int64_t ldy = 0;
+  bool f64 = false;
+};
+int64_t saa_ldy(const sns_matrix& A);
+sns_status launch_form_y(const SaaJob& y, hipStream_t st);
 struct LsqrProb {
   LsqrPlan plan;
   LsqrArgs args;
 };
 struct LsqrJob {
   bool f64 = false;
+  SaaJob saa;  // single-problem SAA-SAS only
   const LsqrArgs* all = nullptr;
   Map mone{}, minv{}, mred{}, mgemv{};
   uint32_t ninv = 0, nred = 0, ngemv = 0;

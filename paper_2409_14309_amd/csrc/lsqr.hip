@@ -96,11 +96,13 @@ __device__ __forceinline__ void lsqr_pass_item(const LsqrArgs& a, uint32_t loc, 
   const LsqrState* __restrict__ st = a.st;
   if (st->done) return;
   const double gamma = st->gamma;
-  const T* __restrict__ A = static_cast<const T*>(a.A);
+  // SAA-SAS runs the residual pass on A and every later pass on Y = A X
+  const bool onY = a.Y != nullptr && st->iter >= 0;
+  const T* __restrict__ A = static_cast<const T*>(onY ? a.Y : a.A);
   const T* __restrict__ uin = static_cast<const T*>(st->iter < 0 ? a.b : a.u);
   T* __restrict__ uout = static_cast<T*>(a.u);
   const double* __restrict__ wv = a.vecs;  // w_pass
-  const int64_t ld = a.ld, m = a.m;
+  const int64_t ld = onY ? a.ldy : a.ld, m = a.m;
   const int n = a.n;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int slot = wid * RPW + lane / LPR, lr = lane % LPR;
@@ -378,7 +380,8 @@ __device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, d
   for (int r = wv; r < kGemvRows; r += nt / 64) {
     const int i = (int)loc * kGemvRows + r;
     if (i < n) {
-      double yi = wave_row_dot(a.Xc, n, i, 0, i + 1, z);
+      // after the residual pass, SAA-SAS works on Y itself: X^T is the identity
+      double yi = (a.Y && !first) ? z[i] : wave_row_dot(a.Xc, n, i, 0, i + 1, z);
       if (!first) yi -= beta * v[i];
       if (lane == 0) {
         ybuf[i] = yi;
@@ -493,7 +496,8 @@ __device__ __forceinline__ void lsqr_xv_item(const LsqrArgs& a, uint32_t loc, in
   for (int r = wv; r < kGemvRows; r += nt / 64) {
     const int i = (int)loc * kGemvRows + r;
     if (i < n) {
-      const double wi = wave_row_dot(a.Xr, n, i, i, n, vec);
+      // the passes after the residual pass read Y = A X under SAA-SAS
+      const double wi = (mode == 0 && a.Y) ? vec[i] : wave_row_dot(a.Xr, n, i, i, n, vec);
       if (lane == 0) out[i] = add0 ? add0[i] + wi : wi;
     }
   }
@@ -722,7 +726,7 @@ void carve_lsqr(Carve& c, const sns_matrix& A, const LsqrPlan& p, LsqrBufs& l) {
 
 LsqrArgs lsqr_args(const sns_matrix& A, const void* b, const LsqrPlan& p, const LsqrBufs& l,
                    const QrBufs& q, int d, int max_iters, double rtol, double* x,
-                   sns_info* info) {
+                   sns_info* info, const void* Y, int64_t ldy) {
   LsqrArgs a;
   const int n = (int)A.n;
   a.A = A.values;
@@ -749,6 +753,8 @@ LsqrArgs lsqr_args(const sns_matrix& A, const void* b, const LsqrPlan& p, const 
   a.info = info;
   a.sighat = 1.0 - sqrt((double)n / (double)d);
   a.stop = rtol > 0.0 ? rtol * (a.sighat > 0.0 ? a.sighat : 1.0) : 0.0;
+  a.Y = Y;
+  a.ldy = ldy;
   return a;
 }
 
@@ -808,7 +814,7 @@ sns_status launch_lsqr_setup(const LsqrJob& j, hipStream_t s) {
   SNS_LAUNCH("tri_inv", k_tri_inv, dim3(grid_for(j.ninv)), dim3(kInvThreads),
              ((size_t)j.maxn + 4096) * sizeof(double), s, j.all, j.minv);
   SNS_HIP_TRY(hipGetLastError());
-  return SNS_OK;
+  return launch_form_y(j.saa, s);
 }
 
 sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t s) {

@@ -82,6 +82,10 @@ void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
     w.lp = make_lsqr_plan(A);
     carve_lsqr(c, A, w.lp, w.l);
   }
+  if (o.refine == 2) {
+    w.ldy = saa_ldy(A);
+    w.Y = c.take<char>((size_t)A.m * w.ldy * elem(A));
+  }
   w.info = c.take<sns_info>(1);
 }
 
@@ -95,8 +99,20 @@ void build_lstsq_jobs(ArgTable& t, Jobs& J, const sns_sketch& sk, const sns_matr
   if (o.refine) {
     LsqrProb lp;
     lp.plan = w.lp;
-    lp.args = lsqr_args(A, b, w.lp, w.l, w.q, (int)sk.d, o.max_iters, o.rtol, x, w.info);
+    lp.args = lsqr_args(A, b, w.lp, w.l, w.q, (int)sk.d, o.max_iters, o.rtol, x, w.info,
+                        o.refine == 2 ? w.Y : nullptr, w.ldy);
     J.lsqr = build_lsqr_job(t, std::vector<LsqrProb>{lp}, A.dtype == SNS_F64);
+    if (o.refine == 2) {
+      SaaJob& y = J.lsqr.saa;
+      y.A = A.values;
+      y.ld = A.ld;
+      y.m = A.m;
+      y.n = (int)A.n;
+      y.X = w.l.Xr;
+      y.Y = w.Y;
+      y.ldy = w.ldy;
+      y.f64 = A.dtype == SNS_F64;
+    }
   }
 }
 
@@ -122,6 +138,7 @@ sns_solve_opts default_opts() {
 
 // Checks of sns_lstsq beyond those of the sketch.
 sns_status check_solve(const sns_sketch& sk, const sns_matrix& A, const sns_solve_opts& o) {
+  if (o.refine < 0 || o.refine > 2) return SNS_ERR_INVALID_ARG;
   if (o.refine && (o.max_iters < 0 || !(o.rtol >= 0.0))) return SNS_ERR_INVALID_ARG;
   if (A.n > 4096 || sk.d > kMaxQrD) return SNS_ERR_SHAPE;
   if (o.refine && A.n > 2048) return SNS_ERR_SHAPE;
@@ -183,6 +200,7 @@ sns_status check_batch(const sns_problem* P, int count) {
     if ((s = check_sketch(&q.sketch, &q.A)) != SNS_OK) return s;
     if (q.sketch.kind != SNS_SKETCH_COUNT || q.A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
     if (q.A.dtype != P[0].A.dtype) return SNS_ERR_DTYPE;
+    if (q.opts.refine == 2) return SNS_ERR_INVALID_ARG;  // SAA-SAS: single-problem calls only
     if ((s = check_solve(q.sketch, q.A, q.opts)) != SNS_OK) return s;
   }
   return SNS_OK;

@@ -64,6 +64,8 @@ struct LstsqWs {
   QrBufs q{};
   LsqrPlan lp;
   LsqrBufs l{};
+  void* Y = nullptr;  // SAA-SAS: A R^{-1}, m rows of stride ldy in A's dtype
+  int64_t ldy = 0;
   sns_info* info = nullptr;
   char* args = nullptr;
 };
