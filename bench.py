@@ -8,7 +8,11 @@ Householder QR of [SA | Sb], triangular solve, then R^{-1}-preconditioned LSQR
 on the full A until the device stop rule certifies residual error <= 1e-6.
 Inputs are resident in HBM before timing starts.  --workload
 gauss_bf16_262144x512 times the same solve with the dense Gaussian sketch
-(d = 2048, bf16 MFMA) of a 262,144 x 512 column-scaled matrix instead.
+(d = 2048, bf16 MFMA) of a 262,144 x 512 column-scaled matrix instead;
+--workload paper_fp64_1000000x1000 times the benchmark family of Sec. 3.1
+(FP64, kappa 1e10, beta 1e-10, n = 1000, d = 4000; --m picks the row count) and
+reports its residual and forward errors against the exact solution built into
+the data.  --solver saa replaces SAP-SAS by SAA-SAS (Y = A R^-1 formed once).
 
 Prints one JSON line: solves/s (value), p50/p99 step latency, the CountSketch
 pass bandwidth, a roofline record for the dominant kernel (timed with HIP
@@ -32,12 +36,17 @@ sys.path.insert(0, ROOT)
 METRIC = "CountSketch HBM GB/s (% peak); LS solves/s + p99 latency at rel-residual 1e-6"
 HBM_PEAK_GBPS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+FP64_PEAK_TFLOPS = 78.6
 # name -> (generator, m, n, d, sketch, data description)
 WORKLOADS = {
     "illcond_fp32_4194304x256": ("dense_ill_conditioned", 4194304, 256, 1024, "count",
                                  "synthetic (seeded; A = G diag(sigma) V^T, kappa 1e6)"),
     "gauss_bf16_262144x512": ("dense_scaled_columns", 262144, 512, 2048, "gaussian",
                               "synthetic (seeded; N(0,1) columns scaled 1 .. 1e-3)"),
+    # Sec. 3.1 benchmark family: kappa 1e10, beta 1e-10, n = 1000, m up to 1e6, fp64
+    "paper_fp64_1000000x1000": ("paper_benchmark_device", 1000000, 1000, 4000, "count",
+                                "synthetic (seeded on the device; A = U diag(sigma) V^T with "
+                                "Haar U, V, sigma log-spaced 1 .. 1e-10, b = A x + 1e-10 r_perp)"),
 }
 
 
@@ -79,14 +88,18 @@ def measured_traffic(kernel: str, src_hash: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(A, b, d, rtol, rows, full_m, kind):
+def cpu_baseline(A, b, d, rtol, rows, full_m, kind, solver="sap"):
     """The oracle (unchanged) on the first `rows` rows, scaled to full m."""
     from threadpoolctl import threadpool_info
 
     from oracle import solve as OSV
     As, bs = A[:rows], b[:rows]
     t0 = time.perf_counter()
-    r = OSV.sap_sas(As, bs, kind, 42, d, 100, rtol=rtol)
+    if solver == "saa":
+        r = OSV.saa_sas(As, bs, kind, 42, d, 100, rtol=rtol,
+                        y_dtype=None if As.dtype == "float64" else As.dtype)
+    else:
+        r = OSV.sap_sas(As, bs, kind, 42, d, 100, rtol=rtol)
     dt = time.perf_counter() - t0
     est = dt * (full_m / rows)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
@@ -283,6 +296,9 @@ def main():
     ap.add_argument("--max-iters", type=int, default=100)
     ap.add_argument("--cpu-rows", type=int, default=1 << 19)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--solver", default="sap", choices=["sap", "saa"],
+                    help="refinement: SAP-SAS (LSQR on A R^-1 applied implicitly) or SAA-SAS "
+                         "(Y = A R^-1 formed once, LSQR on Y)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures a single GPU: the sketch-and-solve path here runs on one "
@@ -310,18 +326,29 @@ def main():
     if args.m:
         m = args.m
     seed = 1001 if kind == "count" else 1003
-    log(f"generating {args.workload}: A {m}x{n} fp32 ...")
-    t0 = time.time()
-    p = getattr(workloads, gen)(m, n, seed=seed)
-    log(f"generated in {time.time() - t0:.1f}s; copying to HBM")
     dev = torch.device("cuda:0")
-    A = torch.from_numpy(p.A).to(dev)
-    b = torch.from_numpy(p.b).to(dev)
+    paper = gen == "paper_benchmark_device"
+    t0 = time.time()
+    x_exact = None
+    if paper:
+        seed = 1005
+        log(f"generating {args.workload} on the device: A {m}x{n} fp64 ...")
+        A, b, x_exact = workloads.paper_benchmark_device(m, n, seed, device=dev)
+        p = None
+    else:
+        log(f"generating {args.workload}: A {m}x{n} fp32 ...")
+        p = getattr(workloads, gen)(m, n, seed=seed)
+        log(f"generated in {time.time() - t0:.1f}s; copying to HBM")
+        A = torch.from_numpy(p.A).to(dev)
+        b = torch.from_numpy(p.b).to(dev)
     torch.cuda.synchronize()
+    log(f"inputs resident in HBM after {time.time() - t0:.1f}s")
+    es = A.element_size()
+    refine = 2 if args.solver == "saa" else 1
 
     sk = sns.sketch_desc(kind, d, 42)
     M = sns.dense(A)
-    o = sns.opts(refine=1, max_iters=args.max_iters, rtol=args.rtol)
+    o = sns.opts(refine=refine, max_iters=args.max_iters, rtol=args.rtol)
     ws = torch.empty(sns.sns_lstsq_workspace_size(sk, M, o), dtype=torch.uint8, device=dev)
     x = torch.empty(n, dtype=torch.float64, device=dev)
     info_buf = torch.zeros(64, dtype=torch.uint8).pin_memory()
@@ -365,13 +392,16 @@ def main():
     # roofline of the dominant kernel (HBM-bound streaming passes)
     dom = max(kt.items(), key=lambda kv: kv[1][1])[0]
     bytes_per = {
-        # one fused LSQR pass: A once, the m-vector u read and written (fp32)
-        "lsqr_pass": 4.0 * m * n + 8.0 * m,
+        # one fused LSQR pass: A (or Y) once, the m-vector u read and written
+        "lsqr_pass": es * m * n + 2.0 * es * m,
         # CountSketch: A and b once, SA and Sb written
-        "cs_gather": 4.0 * m * (n + 1) + 4.0 * d * (n + 1),
+        "cs_gather": es * m * (n + 1) + es * d * (n + 1),
     }
     # Gaussian sketch: 2 d m n flops for G A plus 2 d m for G b
     flops_per = {"gauss_mfma": 2.0 * d * m * n + 2.0 * d * m}
+    # SAA-SAS: Y = A R^-1 with R^-1 upper triangular, n (n + 1) / 2 fp64
+    # multiply-adds per row of A, on the vector ALUs
+    alu_flops_per = {"form_y": float(m) * n * (n + 1)}
 
     def roofline(kname):
         cnt, tot, avg_us = kt[kname]
@@ -387,6 +417,13 @@ def main():
                     "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(ach / BF16_PEAK_TFLOPS, 4), "traffic": None,
                     "flops_per_launch": flops_per[kname], "avg_launch_us": avg_us, "launches": cnt}
+        if kname in alu_flops_per:
+            ach = alu_flops_per[kname] / (avg_us * 1e-6) / 1e12
+            return {"kernel": kname, "bound": "alu", "achieved": round(ach, 2),
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                    "flops_per_launch": alu_flops_per[kname], "avg_launch_us": avg_us,
+                    "launches": cnt}
         return None
 
     roof = roofline(dom)
@@ -401,11 +438,24 @@ def main():
                        "kernel_avg_us": cs[2], "bucket_sort_avg_us": round(sort_us, 2),
                        "GBps_with_sort": round(bytes_per["cs_gather"] / ((cs[2] + sort_us) * 1e-6) / 1e9, 1)}
 
+    form_y = roofline("form_y") if "form_y" in kt else None
+    accuracy = None
+    if x_exact is not None:
+        # x_exact is the least-squares solution and beta the optimal residual
+        dx = x - x_exact
+        accuracy = {"RE": float(torch.linalg.norm(A @ dx) / 1e-10),
+                    "FE": float(torch.linalg.norm(dx) / torch.linalg.norm(x_exact))}
+        log(f"accuracy of the last solve: {accuracy}")
+
     cpu = None
     if not args.no_cpu:
-        rows = min(args.cpu_rows, m)
+        rows = min(args.cpu_rows, m) if not paper else min(args.cpu_rows, m, 100000)
         log(f"timing the CPU oracle on {rows} rows ...")
-        cpu = cpu_baseline(p.A, p.b, d, args.rtol, rows, m, kind)
+        if paper:
+            Ah, bh = A[:rows].cpu().numpy(), b[:rows].cpu().numpy()
+        else:
+            Ah, bh = p.A, p.b
+        cpu = cpu_baseline(Ah, bh, d, args.rtol, rows, m, kind, args.solver)
         log(f"oracle sample took {cpu['seconds_sample']:.2f}s")
 
     out = {
@@ -419,12 +469,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f32 storage, f64 accumulation (QR and LSQR in f64)" if kind == "count" else
+        "dtype": ("f64" if es == 8 else
+                  "f32 storage, f64 accumulation (QR and LSQR in f64)" if kind == "count" else
                   "bf16 x bf16 -> f32 sketch on MFMA; f32 storage, f64 accumulation (QR, LSQR)"),
         "data": data_desc,
         "config": {"workload": args.workload, "m": m, "n": n, "d": d,
                    "sketch": "countsketch" if kind == "count" else "gaussian",
-                   "solver": "SAP-SAS (sketch, Householder QR, LSQR on A R^-1)",
+                   "solver": ("SAA-SAS (sketch, Householder QR, Y = A R^-1 formed, LSQR on Y)"
+                              if refine == 2 else
+                              "SAP-SAS (sketch, Householder QR, LSQR on A R^-1)"),
                    "rtol": args.rtol, "parallelism": "single GPU"},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
                        "p99": round(float(np.percentile(lat, 99)), 4)},
@@ -433,6 +486,8 @@ def main():
         "rel_resid_est": max(ests) if ests else None,
         "countsketch": countsketch,
         "gaussian_sketch": gauss,
+        "form_y": form_y,
+        "accuracy": accuracy,
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_us": round(v[2], 3)}
                     for k, v in kt.items()},

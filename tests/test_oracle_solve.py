@@ -219,3 +219,16 @@ def test_paper_benchmark_generator():
     r = p.b - p.A @ p.x_true
     assert abs(np.linalg.norm(r) - 1e-10) <= 1e-12
     assert np.linalg.norm(p.A.T @ r) <= 1e-14 * np.linalg.norm(r) * 10 + 1e-16
+
+
+def test_paper_benchmark_device_generator_on_cpu():
+    import torch
+    from workloads import paper_benchmark_device
+    A, b, x = paper_benchmark_device(4000, 80, seed=16, device="cpu")
+    A, b, x = A.numpy(), b.numpy(), x.numpy()
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert np.all(np.abs(sv - np.logspace(0.0, -10.0, 80)) <= 1e-12 * sv + 1e-14)
+    r = b - A @ x
+    assert abs(np.linalg.norm(r) - 1e-10) <= 1e-12
+    assert np.linalg.norm(A.T @ r) <= 1e-15
+    assert abs(np.linalg.norm(x) - 1.0) <= 1e-14

@@ -5,5 +5,6 @@ holds none of the sketch-and-solve arithmetic and imports neither the oracle
 nor the product library, so both sides can consume the same inputs.
 """
 from .gen import (CONFIGS, Dense, Sparse, dense_ill_conditioned, dense_gaussian,  # noqa: F401
-                  dense_scaled_columns, paper_benchmark, request_window, serving_pool,
+                  dense_scaled_columns, paper_benchmark, paper_benchmark_device, request_window,
+                  serving_pool,
                   serving_requests, sparse_csr)

@@ -208,6 +208,41 @@ def paper_benchmark(m: int, n: int, seed: int, cond: float = 1e10, beta: float =
                            "cond": cond, "beta": beta})
 
 
+def paper_benchmark_device(m: int, n: int, seed: int, cond: float = 1e10, beta: float = 1e-10,
+                           device="cuda"):
+    """The paper_benchmark family drawn on the device with torch's seeded
+    generator (the paper's largest sizes do not fit a host-side draw in
+    reasonable time).  U is the Q factor of an m x n Gaussian by two rounds of
+    Cholesky QR (positive diagonal, so U is Haar distributed), V the same for
+    an n x n Gaussian; A = U diag(sigma) V^T, ||x|| = 1, b = A x + beta r_perp.
+    Returns (A, b, x) as float64 device tensors; x is the exact least-squares
+    solution and beta the optimal residual norm."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def orth(M):
+        eye = torch.eye(M.shape[1], device=M.device, dtype=M.dtype)
+        for _ in range(2):
+            L = torch.linalg.cholesky(M.T @ M)
+            Linv = torch.linalg.solve_triangular(L, eye, upper=False)  # small n x n solve
+            M = M @ Linv.T
+        return M
+
+    U = orth(torch.randn(m, n, generator=g, device=device, dtype=torch.float64))
+    V = orth(torch.randn(n, n, generator=g, device=device, dtype=torch.float64))
+    sigma = torch.logspace(0.0, -float(np.log10(cond)), n, device=device, dtype=torch.float64)
+    A = (U * sigma) @ V.T
+    x = torch.randn(n, generator=g, device=device, dtype=torch.float64)
+    x /= torch.linalg.norm(x)
+    z = torch.randn(m, generator=g, device=device, dtype=torch.float64)
+    z -= U @ (U.T @ z)
+    z /= torch.linalg.norm(z)
+    b = A @ x + beta * z
+    del U, z
+    return A, b, x
+
+
 # Named workload configurations (sizes, sketch, solver settings).
 CONFIGS = {
     "plain_fp64_20000x50": dict(gen="dense_gaussian", m=20000, n=50, d=200, dtype="f64",
