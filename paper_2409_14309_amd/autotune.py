@@ -7,6 +7,7 @@ m range around the swept m (geometric midpoints between neighbours).  The
 table is written where the Python binding loads it from.
 
     python -m paper_2409_14309_amd.autotune [--out PATH] [--quick]
+    python -m paper_2409_14309_amd.autotune --merge --f64-n 1000   # add shapes to the table
 """
 from __future__ import annotations
 
@@ -18,7 +19,7 @@ import time
 F32_N = (16, 32, 64, 128, 256, 512, 1024, 2048)
 F64_N = (16, 32, 50, 64, 128, 256, 512)
 MS = (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22)
-MAX_BYTES = 8 << 30
+MAX_BYTES = 16 << 30
 
 
 def sweep(dtype_code: int, ns, ms, reps: int, log):
@@ -51,6 +52,10 @@ def main(argv=None):
     ap.add_argument("--out", default=None, help="table path (default: next to libsns.so)")
     ap.add_argument("--quick", action="store_true", help="few shapes (for tests)")
     ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--merge", action="store_true",
+                    help="keep the current table and add or replace only the swept shapes")
+    ap.add_argument("--f32-n", type=int, nargs="*", default=None, help="fp32 widths to sweep")
+    ap.add_argument("--f64-n", type=int, nargs="*", default=None, help="fp64 widths to sweep")
     args = ap.parse_args(argv)
 
     def log(msg):
@@ -59,9 +64,12 @@ def main(argv=None):
     from paper_2409_14309_amd._binding import TUNING_PATH
     out = args.out or TUNING_PATH
     sns.load()
-    sns.sns_tune_clear()  # time against the built-in rule only
+    if not args.merge:
+        sns.sns_tune_clear()  # time against the built-in rule only
     t0 = time.time()
     f32_n, f64_n, ms = (F32_N, F64_N, MS) if not args.quick else ((64,), (50,), (1 << 14, 1 << 18))
+    if args.f32_n is not None or args.f64_n is not None:
+        f32_n, f64_n = tuple(args.f32_n or ()), tuple(args.f64_n or ())
     entries = sweep(sns.SNS_F32, f32_n, ms, args.reps, log) + sweep(sns.SNS_F64, f64_n, ms, args.reps, log)
     for e in entries:
         sns.sns_tune_set(e)
