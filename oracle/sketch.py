@@ -15,6 +15,11 @@ Readings fixed here (the paper is silent on them):
     i & 1 takes words (2*lane, 2*lane+1) as (w_h, w_s).  The bucket is the
     multiply-shift reduction h = (w_h * d) >> 32 and the sign is +1 when the
     top bit of w_s is clear, else -1.  Entries of S are +-1 with no scale.
+  * sparse sign embedding (the sparse sketch family of Sec. 1.2.2 with zeta
+    nonzeros per column): nonzero k of column i uses the CountSketch rule
+    with counter (j mod 2^32, j >> 32, k, 0), so k = 0 is the CountSketch
+    itself; S is the sum of the zeta one-per-column matrices (entries +-1,
+    no scale; a collision of two entries in one row adds them).
   * Gaussian sketch: entry G[k, i] is the table value T[q] where q is one
     byte of Philox4x32-10 at counter (j mod 2^32, j >> 32, k, 1), j = i >> 4,
     and key seed: byte (i & 15) of the little-endian 16-byte output, so one
@@ -46,6 +51,13 @@ def countsketch_hash(seed: int, d: int, i0: int, count: int):
 
     Returns (h uint32[count], s int8[count]).
     """
+    return sparse_sign_hash(seed, d, i0, count, 0)
+
+
+def sparse_sign_hash(seed: int, d: int, i0: int, count: int, k: int):
+    """Bucket and sign of nonzero k of columns i0 .. i0+count-1 of the sparse
+    sign embedding: the CountSketch rule with counter word 2 set to k (k = 0 is
+    the CountSketch hash itself).  Returns (h uint32[count], s int8[count])."""
     if count == 0:
         return np.zeros(0, np.uint32), np.zeros(0, np.int8)
     i = np.uint64(i0) + np.arange(count, dtype=np.uint64)
@@ -54,7 +66,8 @@ def countsketch_hash(seed: int, d: int, i0: int, count: int):
     c0 = (j & np.uint64(0xFFFFFFFF)).astype(np.uint32)
     c1 = (j >> np.uint64(32)).astype(np.uint32)
     zero = np.zeros_like(c0)
-    w0, w1, w2, w3 = philox4x32(c0, c1, zero + TAG_COUNT, zero, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    w0, w1, w2, w3 = philox4x32(c0, c1, zero + np.uint32(k), zero + TAG_COUNT,
+                                seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
     w_h = np.where(lane, w2, w0)
     w_s = np.where(lane, w3, w1)
     h = ((w_h.astype(np.uint64) * np.uint64(d)) >> np.uint64(32)).astype(np.uint32)
@@ -77,6 +90,32 @@ def countsketch_apply(A, b, seed: int, d: int):
     """
     m = A.shape[0]
     S = countsketch_matrix(seed, d, m)
+    if sp.issparse(A):
+        SA = (S @ A.astype(np.float64)).toarray()
+    else:
+        SA = S @ np.asarray(A, dtype=np.float64)
+    Sb = None if b is None else S @ np.asarray(b, dtype=np.float64)
+    return np.asarray(SA), Sb
+
+
+def sparse_sign_matrix(seed: int, d: int, m: int, zeta: int) -> sp.csr_matrix:
+    """The sparse sign embedding with zeta nonzeros per column, as the sum of
+    zeta independent CountSketch matrices: S[h_k(i), i] += s_k(i) for
+    k = 0 .. zeta-1 (two of a column's entries that land in one row add)."""
+    rows, cols, vals = [], [], []
+    for k in range(zeta):
+        h, s = sparse_sign_hash(seed, d, 0, m, k)
+        rows.append(h.astype(np.int64))
+        cols.append(np.arange(m))
+        vals.append(s.astype(np.float64))
+    S = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(d, m))
+    return S.tocsr()  # duplicates summed
+
+
+def sparse_sign_apply(A, b, seed: int, d: int, zeta: int):
+    """SA = S A and Sb = S b in float64 with S from sparse_sign_matrix."""
+    S = sparse_sign_matrix(seed, d, A.shape[0], zeta)
     if sp.issparse(A):
         SA = (S @ A.astype(np.float64)).toarray()
     else:

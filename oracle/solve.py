@@ -31,7 +31,7 @@ import scipy.sparse as sp
 from .lsqr import lsqr
 from .qr import (back_substitution, forward_substitution_transposed,
                  householder_qr_augmented, rank_deficient)
-from .sketch import countsketch_apply, gaussian_apply
+from .sketch import countsketch_apply, gaussian_apply, sparse_sign_apply
 
 
 @dataclass
@@ -47,9 +47,11 @@ class SolveResult:
     arnorm: float = float("nan")
 
 
-def sketch(A, b, kind: str, seed: int, d: int):
+def sketch(A, b, kind: str, seed: int, d: int, zeta: int = 1):
     if kind == "count":
         return countsketch_apply(A, b, seed, d)
+    if kind == "sparse":
+        return sparse_sign_apply(A, b, seed, d, zeta)
     if kind == "gaussian":
         return gaussian_apply(A, b, seed, d)
     raise ValueError(kind)
@@ -69,9 +71,10 @@ def sigma_hat(n: int, d: int) -> float:
     return 1.0 - math.sqrt(n / d)
 
 
-def sketch_and_solve(A, b, kind: str, seed: int, d: int, SA=None, Sb=None) -> SolveResult:
+def sketch_and_solve(A, b, kind: str, seed: int, d: int, SA=None, Sb=None,
+                     zeta: int = 1) -> SolveResult:
     if SA is None:
-        SA, Sb = sketch(A, b, kind, seed, d)
+        SA, Sb = sketch(A, b, kind, seed, d, zeta)
     R, c, rho, _, _ = householder_qr_augmented(SA, Sb)
     rd = rank_deficient(R)
     x0 = back_substitution(R, c)
@@ -79,9 +82,9 @@ def sketch_and_solve(A, b, kind: str, seed: int, d: int, SA=None, Sb=None) -> So
 
 
 def sap_sas(A, b, kind: str, seed: int, d: int, max_iters: int, rtol: float = 0.0,
-            SA=None, Sb=None) -> SolveResult:
+            SA=None, Sb=None, zeta: int = 1) -> SolveResult:
     """SAP-SAS; rtol = 0 runs exactly max_iters LSQR iterations."""
-    base = sketch_and_solve(A, b, kind, seed, d, SA, Sb)
+    base = sketch_and_solve(A, b, kind, seed, d, SA, Sb, zeta)
     R = base.R
     n = R.shape[0]
     if sp.issparse(A):
@@ -111,9 +114,9 @@ def form_y(A, R: np.ndarray) -> np.ndarray:
 
 
 def saa_sas(A, b, kind: str, seed: int, d: int, max_iters: int, rtol: float = 0.0,
-            SA=None, Sb=None, y_dtype=None) -> SolveResult:
+            SA=None, Sb=None, y_dtype=None, zeta: int = 1) -> SolveResult:
     """SAA-SAS; rtol = 0 runs exactly max_iters LSQR iterations."""
-    base = sketch_and_solve(A, b, kind, seed, d, SA, Sb)
+    base = sketch_and_solve(A, b, kind, seed, d, SA, Sb, zeta)
     R = base.R
     n = R.shape[0]
     Y = form_y(A, R)

@@ -6,6 +6,11 @@ and an explicit row loop, sketching the identity returns S itself, the map is
 linear, row blocks sketched with global offsets add up to the whole, and
 E||Sx||^2 = ||x||^2 (statistical).  Hash statistics: bucket counts uniform
 (chi-square), signs balanced, consecutive rows independent.
+Sparse sign embedding: zeta = 1 is the CountSketch itself; S is the sum of
+zeta matrices with one +-1 per column (built here entry by entry from the
+per-k hashes), the sparse product equals that dense product and an explicit
+loop, the hashes of different k are independent (collision rate 1/d), and
+E||Sx||^2 = zeta ||x||^2 (statistical).
 Gaussian table: symmetric, monotone, every entry the bfloat16 rounding of the
 normal quantile computed independently by bisection on math.erfc; bfloat16
 rounding agrees with torch's float32 -> bfloat16 conversion.
@@ -206,3 +211,66 @@ def test_gaussian_sketch_isotropy():
     assert np.max(np.abs(np.diag(C) - var)) < 6 * var * math.sqrt(2.0 / d)
     off = C - np.diag(np.diag(C))
     assert np.max(np.abs(off)) < 6 * var / math.sqrt(d)
+
+
+# ------------------------------------------------------ sparse sign ----
+
+def test_sparse_sign_zeta_one_is_countsketch():
+    p = dense_gaussian(900, 7, seed=5)
+    a = S.countsketch_apply(p.A, p.b, 13, 40)
+    c = S.sparse_sign_apply(p.A, p.b, 13, 40, 1)
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+    h0, s0 = S.countsketch_hash(13, 40, 0, 900)
+    h1, s1 = S.sparse_sign_hash(13, 40, 0, 900, 0)
+    assert np.array_equal(h0, h1) and np.array_equal(s0, s1)
+
+
+@pytest.mark.parametrize("zeta", [2, 3, 8])
+def test_sparse_sign_structure_product_and_loop(zeta):
+    m, d, n, seed = 600, 37, 5, 21
+    rng = np.random.default_rng(zeta)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    # entry by entry: column i gets s_k(i) at row h_k(i) for each k
+    M = np.zeros((d, m))
+    per_k = []
+    for k in range(zeta):
+        h, sg = S.sparse_sign_hash(seed, d, 0, m, k)
+        Mk = np.zeros((d, m))
+        for i in range(m):
+            Mk[h[i], i] = sg[i]
+        assert np.all((Mk != 0).sum(axis=0) == 1)
+        per_k.append(Mk)
+        M += Mk
+    assert np.array_equal(S.sparse_sign_matrix(seed, d, m, zeta).toarray(), M)
+    SA, Sb = S.sparse_sign_apply(A, b, seed, d, zeta)
+    np.testing.assert_allclose(SA, M @ A, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Sb, M @ b, rtol=0, atol=1e-12)
+    # explicit loop over columns of S (rows of A), all k of a row in turn
+    SAl = np.zeros((d, n))
+    for i in range(m):
+        for Mk in per_k:
+            r = int(np.flatnonzero(Mk[:, i])[0])
+            SAl[r] += Mk[r, i] * A[i]
+    np.testing.assert_allclose(SA, SAl, rtol=0, atol=1e-12)
+
+
+def test_sparse_sign_hashes_independent_across_k():
+    d, m = 64, 200000
+    h0, s0 = S.sparse_sign_hash(3, d, 0, m, 0)
+    h1, s1 = S.sparse_sign_hash(3, d, 0, m, 1)
+    rate = float(np.mean(h0 == h1))
+    assert abs(rate - 1.0 / d) < 5 * math.sqrt((1.0 / d) / m)
+    agree = float(np.mean(s0 == s1))
+    assert abs(agree - 0.5) < 5 * math.sqrt(0.25 / m)
+
+
+def test_sparse_sign_norm_scales_with_zeta():
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal(300)
+    vals = []
+    for seed in range(300):
+        sx, _ = S.sparse_sign_apply(x[:, None], None, seed, 20, 4)
+        vals.append(float(np.sum(sx ** 2)))
+    vals = np.array(vals)
+    assert abs(vals.mean() - 4 * (x @ x)) < 5 * vals.std() / math.sqrt(len(vals))

@@ -232,3 +232,19 @@ def test_paper_benchmark_device_generator_on_cpu():
     assert abs(np.linalg.norm(r) - 1e-10) <= 1e-12
     assert np.linalg.norm(A.T @ r) <= 1e-15
     assert abs(np.linalg.norm(x) - 1.0) <= 1e-14
+
+
+def test_sparse_sign_sap_sas_and_embedding_quality():
+    p = dense_ill_conditioned(40000, 32, seed=17, cond=1e5)
+    xs = MT.lstsq_exact(p.A, p.b)
+    r = SV.sap_sas(p.A, p.b, "sparse", 42, 128, 100, rtol=1e-6, zeta=4)
+    assert MT.metrics(p.A, p.b, r.x, xs)["RE"] <= 1e-6
+    # at d = 2n the zeta = 8 embedding preconditions better than one nonzero per column
+    q = dense_gaussian(20000, 32, seed=18)
+    k1, k8 = [], []
+    for seed in range(5):
+        for zeta, out in ((1, k1), (8, k8)):
+            R = SV.sketch_and_solve(q.A, q.b, "sparse", seed, 64, zeta=zeta).R
+            sv = np.linalg.svd(q.A @ np.linalg.inv(R), compute_uv=False)
+            out.append(sv.max() / sv.min())
+    assert np.mean(k8) < np.mean(k1)
