@@ -60,8 +60,9 @@ typedef enum { SNS_DENSE_ROWMAJOR = 0, SNS_CSR = 1 } sns_layout;
 
 /* Sketch operators (Sec. 1.2.1 and 1.2.2). */
 typedef enum {
-  SNS_SKETCH_COUNT = 0,    /* Clarkson-Woodruff CountSketch: one +-1 per column of S */
-  SNS_SKETCH_GAUSSIAN = 1  /* dense Gaussian sketch, bf16 inputs, fp32 accumulation */
+  SNS_SKETCH_COUNT = 0,       /* Clarkson-Woodruff CountSketch: one +-1 per column of S */
+  SNS_SKETCH_GAUSSIAN = 1,    /* dense Gaussian sketch, bf16 inputs, fp32 accumulation */
+  SNS_SKETCH_SPARSE_SIGN = 2  /* sparse sign embedding: zeta +-1 entries per column of S */
 } sns_sketch_kind;
 
 /* A tall matrix.  Dense: values (m x n row-major, leading dimension ld).
@@ -92,11 +93,18 @@ typedef struct {
  * Gaussian (Sec. 1.2.1): S = d^{-1/2} G with G[k, i] = T[q], q the byte
  *   (i & 15) of Philox4x32-10(counter (j mod 2^32, j >> 32, k, 1), key as
  *   above), j = i >> 4, T[q] = bf16(Phi^{-1}((q + 1/2) / 256)).  The product
- *   uses bf16(A) and bf16(b) (round to nearest even). */
+ *   uses bf16(A) and bf16(b) (round to nearest even).
+ * Sparse sign embedding (the sparse family of Sec. 1.2.2 with `zeta` nonzeros
+ *   per column): S = sum over k = 0 .. zeta-1 of CountSketch matrices S_k,
+ *   where S_k uses the CountSketch rule above with counter word 2 set to k
+ *   (so zeta = 1 is the CountSketch); entries +-1 without scale, and two
+ *   entries of a column that land in one row add.  Dense A only; zeta in
+ *   1..64 with zeta * m < 2^31.  `zeta` is ignored by the other kinds. */
 typedef struct {
   sns_sketch_kind kind;
   int64_t d;
   uint64_t seed;
+  int32_t zeta;
 } sns_sketch;
 
 typedef struct {
@@ -195,7 +203,7 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
 
 /* One problem of a batch (sns_lstsq_batched). */
 typedef struct {
-  sns_sketch sketch;    /* CountSketch (SNS_SKETCH_COUNT) */
+  sns_sketch sketch;    /* CountSketch or sparse sign embedding */
   sns_matrix A;         /* dense row-major */
   const void* b;        /* device, m entries of A's dtype */
   double* x;            /* device fp64[n], the answer */

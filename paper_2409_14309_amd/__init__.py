@@ -42,11 +42,11 @@ def _workspace(nbytes: int, device):
 
 
 def sketch(A, b=None, kind: str = "count", d: int = None, seed: int = 42, accum_fp64: bool = False,
-           stream=None):
+           stream=None, zeta: int = 1):
     """SA, Sb = S A, S b for a dense device tensor or a CsrMatrix A (and
     optional b)."""
     import torch
-    sk = sketch_desc(kind, d, seed)
+    sk = sketch_desc(kind, d, seed, zeta)
     M = _describe(A)
     ws = _workspace(sns_sketch_workspace_size(sk, M), A.device)
     SA = torch.empty((d, A.shape[1]), dtype=A.dtype, device=A.device)
@@ -59,11 +59,12 @@ REFINE = {False: 0, True: 1, 0: 0, 1: 1, 2: 2, "sas": 0, "sap": 1, "saa": 2}
 
 
 def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine=False,
-          max_iters: int = 100, rtol: float = 1e-6, accum_fp64: bool = False, stream=None):
+          max_iters: int = 100, rtol: float = 1e-6, accum_fp64: bool = False, stream=None,
+          zeta: int = 1):
     """x (float64 device tensor) and Info for min ||A x - b||.  refine: False /
     "sas" (plain sketch-and-solve), True / "sap" (SAP-SAS) or "saa" (SAA-SAS)."""
     import torch
-    sk = sketch_desc(kind, d, seed)
+    sk = sketch_desc(kind, d, seed, zeta)
     M = _describe(A)
     r = REFINE[refine]
     o = opts(r, max_iters if r else 0, rtol if r else 0.0, int(accum_fp64))

@@ -19,7 +19,7 @@ STATUS_NAMES = ["SNS_OK", "SNS_ERR_INVALID_ARG", "SNS_ERR_SHAPE", "SNS_ERR_DTYPE
 SNS_ERR_QUEUE_FULL, SNS_ERR_NOT_READY = 8, 9
 SNS_F32, SNS_F64 = 0, 1
 SNS_DENSE_ROWMAJOR, SNS_CSR = 0, 1
-SNS_SKETCH_COUNT, SNS_SKETCH_GAUSSIAN = 0, 1
+SNS_SKETCH_COUNT, SNS_SKETCH_GAUSSIAN, SNS_SKETCH_SPARSE_SIGN = 0, 1, 2
 
 
 class SnsError(RuntimeError):
@@ -36,7 +36,7 @@ class Matrix(C.Structure):
 
 
 class Sketch(C.Structure):
-    _fields_ = [("kind", C.c_int), ("d", C.c_int64), ("seed", C.c_uint64)]
+    _fields_ = [("kind", C.c_int), ("d", C.c_int64), ("seed", C.c_uint64), ("zeta", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -192,8 +192,14 @@ def csr(row_ptr, col_idx, values, m: int, n: int) -> Matrix:
                   col_idx.data_ptr(), values.numel())
 
 
-def sketch_desc(kind: str, d: int, seed: int) -> Sketch:
-    return Sketch(SNS_SKETCH_COUNT if kind == "count" else SNS_SKETCH_GAUSSIAN, d, seed)
+SKETCH_KINDS = {"count": SNS_SKETCH_COUNT, "gaussian": SNS_SKETCH_GAUSSIAN,
+                "sparse": SNS_SKETCH_SPARSE_SIGN}
+
+
+def sketch_desc(kind: str, d: int, seed: int, zeta: int = 1) -> Sketch:
+    """kind: "count" (CountSketch), "gaussian", or "sparse" (sparse sign
+    embedding with zeta nonzeros per column)."""
+    return Sketch(SKETCH_KINDS[kind], d, seed, zeta)
 
 
 def opts(refine: int = 0, max_iters: int = 0, rtol: float = 0.0, accum_fp64: int = 0) -> SolveOpts:

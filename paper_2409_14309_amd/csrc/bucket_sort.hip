@@ -13,6 +13,17 @@ namespace sns {
 
 namespace {
 
+// Hash k of row i of the sparse sign embedding: the CountSketch rule with
+// counter word 2 = k (k = 0 is cs_hash).
+__device__ __forceinline__ Hash ss_hash(uint64_t seed, uint32_t d, uint64_t i, uint32_t k) {
+  const uint64_t j = i >> 1;
+  const U4 w = philox4x32_10(U4{(uint32_t)j, (uint32_t)(j >> 32), k, 0u}, (uint32_t)seed,
+                             (uint32_t)(seed >> 32));
+  const uint32_t wh = (i & 1) ? w.z : w.x;
+  const uint32_t ws = (i & 1) ? w.w : w.y;
+  return Hash{(uint32_t)(((uint64_t)wh * d) >> 32), (ws >> 31) != 0u};
+}
+
 // Row hashes for the test entry point.
 __global__ void k_hash(uint64_t seed, uint32_t d, int64_t i0, int64_t count, uint32_t* h,
                        int8_t* s) {
@@ -38,7 +49,12 @@ __device__ __forceinline__ void sort_count_item(const SortArgs& a, uint32_t loc,
   const int64_t m = a.mdev ? (int64_t)*a.mdev : a.m;  // key count known only on the device
   if (wb < a.nwb) {
     const int64_t r0 = wb * a.rw, r1 = min(m, r0 + a.rw);  // r0 is even
-    if (a.rows) {
+    if (a.zeta > 1) {  // key t: hash t % zeta of row t / zeta (keys < 2^31)
+      for (int64_t t = r0 + lane; t < r1; t += 64) {
+        const uint32_t row = (uint32_t)t / a.zeta, k = (uint32_t)t - row * a.zeta;
+        atomicAdd(&hist[ss_hash(a.seed, d, row, k).h], 1u);
+      }
+    } else if (a.rows) {
       for (int64_t t = r0 + lane; t < r1; t += 64)
         atomicAdd(&hist[cs_hash(a.seed, d, a.rows[t]).h], 1u);
     } else {
@@ -157,9 +173,16 @@ __device__ __forceinline__ void sort_scatter_item(const SortArgs& a, uint32_t lo
   for (int64_t r = r0; r < r1; r += 64) {
     const int64_t tk = r + lane;
     const bool valid = tk < r1;
-    const int64_t i = rows ? (int64_t)nrow : tk;
+    int64_t i = rows ? (int64_t)nrow : tk;
     if (rows) nrow = tk + 64 < r1 ? rows[tk + 64] : 0u;  // next batch in flight
-    const Hash hs = cs_hash(a.seed, d, (uint64_t)i);
+    Hash hs;
+    if (a.zeta > 1) {
+      const uint32_t row = (uint32_t)tk / a.zeta, k = (uint32_t)tk - row * a.zeta;
+      i = row;
+      hs = ss_hash(a.seed, d, row, k);
+    } else {
+      hs = cs_hash(a.seed, d, (uint64_t)i);
+    }
     const uint32_t h = valid ? hs.h : 0xFFFFFFFFu;
     // rank among the earlier lanes of this batch with the same bucket
     uint32_t rank = 0;
@@ -200,10 +223,11 @@ int sort_waves(uint32_t maxd) {
 
 }  // namespace
 
-SortPlan make_sort_plan(int64_t m, uint32_t d) {
+SortPlan make_sort_plan(int64_t m, uint32_t d, uint32_t zeta) {
   SortPlan p;
   p.m = m;
   p.d = d;
+  p.zeta = zeta < 1 ? 1 : zeta;
   // at most ~4096 wave-blocks, at least 512 keys each, and at least d / 2
   // keys each so the d x nwb count matrix stays within ~2 entries per key
   int64_t rw = (m + 4095) / 4096;
@@ -235,6 +259,7 @@ SortArgs sort_args(const SortPlan& p, uint64_t seed, const void* b, const SortBu
   a.seg = p.seg;
   a.nseg = p.nseg;
   a.d = p.d;
+  a.zeta = p.zeta;
   a.rows = rows;
   a.mdev = mdev;
   a.b = b;

@@ -187,7 +187,7 @@ void dispatch_lpr(const GatherLaunch& g, hipStream_t st) {
 
 }  // namespace
 
-GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64) {
+GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64, int64_t keys) {
   GatherPlan g;
   const size_t es = A.dtype == SNS_F64 ? 8 : 4;
   const int vmax = (int)(16 / es);
@@ -203,7 +203,7 @@ GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64) {
   // enough work-groups to fill the device, each segment keeping >= 256 rows
   const int64_t wgs = (int64_t)d * g.coltiles;
   int64_t nseg = (1024 + wgs - 1) / wgs;
-  const int64_t maxseg = A.m / ((int64_t)d * 256);
+  const int64_t maxseg = (keys >= 0 ? keys : A.m) / ((int64_t)d * 256);
   if (nseg > maxseg) nseg = maxseg;
   if (nseg < 1) nseg = 1;
   if (nseg > 64) nseg = 64;

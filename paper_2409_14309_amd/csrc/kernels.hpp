@@ -104,14 +104,19 @@ constexpr size_t kArgTableAlign = 16;
 // perm[m] (row id with the sign in bit 31, rows ascending inside a bucket),
 // bucket_ptr[d+1], and, when b is given, bperm[m] = s(i) b[i] in perm order.
 struct SortPlan {
-  int64_t m = 0;
+  int64_t m = 0;        // keys: rows x zeta
   uint32_t d = 0;
+  uint32_t zeta = 1;    // nonzeros per column of S (key t: row t / zeta, hash t % zeta)
   int64_t rw = 0;       // rows per wave-block
   int64_t nwb = 0;      // wave-blocks
   int64_t seg = 64;     // wave-blocks per scan segment
   int64_t nseg = 0;     // scan segments
 };
-SortPlan make_sort_plan(int64_t m, uint32_t d);
+SortPlan make_sort_plan(int64_t keys, uint32_t d, uint32_t zeta = 1);
+// Nonzeros per column of the sketch (1 for the CountSketch).
+inline uint32_t sketch_zeta(const sns_sketch& sk) {
+  return sk.kind == SNS_SKETCH_SPARSE_SIGN ? (uint32_t)sk.zeta : 1u;
+}
 struct SortBufs {
   uint32_t* perm;
   void* bperm;
@@ -127,6 +132,7 @@ struct SortArgs {
   uint64_t seed;
   int64_t m, rw, nwb, seg, nseg;
   uint32_t d;
+  uint32_t zeta;  // > 1: key t is hash t % zeta of row t / zeta (no row list)
   const uint32_t* rows;
   const uint32_t* mdev;
   const void* b;
@@ -157,7 +163,7 @@ struct GatherPlan {
   int vec = 1, lpr = 64, ct = 64, coltiles = 1, nseg = 1;
   bool acc64 = false;
 };
-GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64);
+GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64, int64_t keys = -1);
 size_t gather_partial_bytes(const GatherPlan& g, const sns_matrix& A, uint32_t d);
 struct GatherArgs {
   const void* A;

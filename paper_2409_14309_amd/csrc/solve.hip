@@ -28,9 +28,16 @@ sns_status check_matrix(const sns_matrix* A) {
 
 sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A) {
   if (!sk) return SNS_ERR_INVALID_ARG;
-  if (sk->kind != SNS_SKETCH_COUNT && sk->kind != SNS_SKETCH_GAUSSIAN) return SNS_ERR_INVALID_ARG;
+  if (sk->kind != SNS_SKETCH_COUNT && sk->kind != SNS_SKETCH_GAUSSIAN &&
+      sk->kind != SNS_SKETCH_SPARSE_SIGN)
+    return SNS_ERR_INVALID_ARG;
   if (sk->d < 1 || sk->d > kMaxD) return SNS_ERR_SHAPE;
+  if (sk->kind == SNS_SKETCH_SPARSE_SIGN && (sk->zeta < 1 || sk->zeta > 64))
+    return SNS_ERR_INVALID_ARG;
   if (A) {
+    if (sk->kind == SNS_SKETCH_SPARSE_SIGN && A->layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+    if (sk->kind == SNS_SKETCH_SPARSE_SIGN && (int64_t)sk->zeta * A->m > kMaxRows)
+      return SNS_ERR_SHAPE;
     if (sk->d < A->n || sk->d > A->m) return SNS_ERR_SHAPE;
     if (sk->kind == SNS_SKETCH_GAUSSIAN && A->dtype != SNS_F32) return SNS_ERR_DTYPE;
     if (sk->kind == SNS_SKETCH_GAUSSIAN && A->layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
@@ -41,8 +48,9 @@ sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A) {
 
 void carve_sketch(Carve& c, const sns_sketch& sk, const sns_matrix& A, bool with_b, bool acc64,
                   SketchWs& w) {
-  w.sp = make_sort_plan(A.m, (uint32_t)sk.d);
-  w.gp = make_gather_plan(A, (uint32_t)sk.d, acc64);
+  const uint32_t zeta = sketch_zeta(sk);
+  w.sp = make_sort_plan(A.m * zeta, (uint32_t)sk.d, zeta);
+  w.gp = make_gather_plan(A, (uint32_t)sk.d, acc64, A.m * zeta);
   carve_sort(c, w.sp, with_b ? elem(A) : 0, w.sb);
   const size_t pb = gather_partial_bytes(w.gp, A, (uint32_t)sk.d);
   w.part = pb ? (void*)c.take<char>(pb) : nullptr;
@@ -91,7 +99,7 @@ void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
 
 void build_lstsq_jobs(ArgTable& t, Jobs& J, const sns_sketch& sk, const sns_matrix& A,
                       const void* b, double* x, const sns_solve_opts& o, const LstsqWs& w) {
-  if (sk.kind == SNS_SKETCH_COUNT && A.layout == SNS_DENSE_ROWMAJOR)
+  if (sk.kind != SNS_SKETCH_GAUSSIAN && A.layout == SNS_DENSE_ROWMAJOR)
     add_sketch_jobs(t, J, sk, A, b, w.SA, w.Sb, w.sw);
   const std::vector<QrArgs> qa{
       qr_args(sk.d, A.n, w.SA, A.n, w.Sb, w.q, w.q.xw, nullptr, w.info)};
@@ -198,7 +206,7 @@ sns_status check_batch(const sns_problem* P, int count) {
     sns_status s = check_matrix(&q.A);
     if (s != SNS_OK) return s;
     if ((s = check_sketch(&q.sketch, &q.A)) != SNS_OK) return s;
-    if (q.sketch.kind != SNS_SKETCH_COUNT || q.A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+    if (q.sketch.kind == SNS_SKETCH_GAUSSIAN || q.A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
     if (q.A.dtype != P[0].A.dtype) return SNS_ERR_DTYPE;
     if (q.opts.refine == 2) return SNS_ERR_INVALID_ARG;  // SAA-SAS: single-problem calls only
     if ((s = check_solve(q.sketch, q.A, q.opts)) != SNS_OK) return s;
