@@ -1,5 +1,6 @@
-"""Sketching operators of the oracle: CountSketch (Clarkson-Woodruff) and the
-Gaussian sketch, in float64.
+"""Sketching operators of the oracle: CountSketch (Clarkson-Woodruff), the
+sparse sign embedding, the Gaussian sketch and the subsampled randomized
+Hadamard transform, in float64.
 
 TEST INFRASTRUCTURE ONLY: nothing in the product path may import this module.
 
@@ -211,4 +212,77 @@ def gaussian_apply(A, b, seed: int, d: int):
     scale = 1.0 / math.sqrt(d)
     SA = scale * (G @ bf16_round(A))
     Sb = None if b is None else scale * (G @ bf16_round(np.asarray(b, dtype=np.float64)))
+    return SA, Sb
+
+
+# --------------------------------------------------------------------------
+# Subsampled randomized Hadamard transform (the Hadamard sketch of Sec. 1.2.1)
+# --------------------------------------------------------------------------
+#
+# Readings fixed here: A is padded with zero rows to m' = 2^L >= m rows;
+# S = d^{-1/2} P H D with D = diag(s(i)) random signs, H the unnormalised
+# Sylvester-Hadamard matrix (H[r, i] = (-1)^popcount(r & i)) and P the
+# selection of d rows r_0 .. r_{d-1} drawn uniformly from [0, m') with
+# replacement.  Generator words: s(i) is +1 when the top bit of word (i & 3)
+# of Philox4x32-10 at counter (i >> 2 mod 2^32, i >> 34, 0, 2) is clear;
+# r_k = (w * m') >> 32 with w word (k & 3) of Philox4x32-10 at counter
+# (k >> 2 mod 2^32, k >> 34, 0, 3); key = seed as for the other sketches.
+
+TAG_HAD_SIGN = 2
+TAG_HAD_ROWS = 3
+
+
+def _words_by_index(seed: int, idx: np.ndarray, tag: int) -> np.ndarray:
+    idx = idx.astype(np.uint64)
+    q = idx >> np.uint64(2)
+    c0 = (q & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    c1 = (q >> np.uint64(32)).astype(np.uint32)
+    zero = np.zeros_like(c0)
+    w = philox4x32(c0, c1, zero, zero + np.uint32(tag), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    lane = (idx & np.uint64(3)).astype(np.int64)
+    return np.choose(lane, w)
+
+
+def hadamard_padded_rows(m: int) -> int:
+    """m' = the smallest power of two >= m."""
+    return 1 << max(0, (int(m) - 1).bit_length())
+
+
+def hadamard_signs(seed: int, m: int) -> np.ndarray:
+    """s(i) in {+1, -1} for i in [0, m), int8."""
+    w = _words_by_index(seed, np.arange(m, dtype=np.uint64), TAG_HAD_SIGN)
+    return (1 - 2 * (w >> np.uint32(31)).astype(np.int16)).astype(np.int8)
+
+
+def hadamard_rows(seed: int, d: int, mp: int) -> np.ndarray:
+    """The d sampled rows r_k of H D A, int64."""
+    w = _words_by_index(seed, np.arange(d, dtype=np.uint64), TAG_HAD_ROWS)
+    return ((w.astype(np.uint64) * np.uint64(mp)) >> np.uint64(32)).astype(np.int64)
+
+
+def hadamard_sign_matrix(rows: np.ndarray, mp: int) -> np.ndarray:
+    """H[rows, :] for the unnormalised Sylvester-Hadamard matrix of order mp:
+    entry (k, i) = (-1)^popcount(rows[k] & i)."""
+    i = np.arange(mp, dtype=np.int64)
+    x = rows[:, None] & i[None, :]
+    pc = np.zeros(x.shape, dtype=np.int64)
+    while np.any(x):
+        pc += x & 1
+        x >>= 1
+    return 1.0 - 2.0 * (pc & 1)
+
+
+def hadamard_matrix(seed: int, d: int, m: int) -> np.ndarray:
+    """S = d^{-1/2} P H D restricted to the m real rows (dense, float64)."""
+    mp = hadamard_padded_rows(m)
+    H = hadamard_sign_matrix(hadamard_rows(seed, d, mp), mp)[:, :m]
+    return H * hadamard_signs(seed, m).astype(np.float64)[None, :] / math.sqrt(d)
+
+
+def hadamard_apply(A, b, seed: int, d: int):
+    """SA = S A and Sb = S b in float64 with S from hadamard_matrix."""
+    A = np.asarray(A, dtype=np.float64)
+    S = hadamard_matrix(seed, d, A.shape[0])
+    SA = S @ A
+    Sb = None if b is None else S @ np.asarray(b, dtype=np.float64)
     return SA, Sb

@@ -31,7 +31,7 @@ import scipy.sparse as sp
 from .lsqr import lsqr
 from .qr import (back_substitution, forward_substitution_transposed,
                  householder_qr_augmented, rank_deficient)
-from .sketch import countsketch_apply, gaussian_apply, sparse_sign_apply
+from .sketch import countsketch_apply, gaussian_apply, hadamard_apply, sparse_sign_apply
 
 
 @dataclass
@@ -52,6 +52,8 @@ def sketch(A, b, kind: str, seed: int, d: int, zeta: int = 1):
         return countsketch_apply(A, b, seed, d)
     if kind == "sparse":
         return sparse_sign_apply(A, b, seed, d, zeta)
+    if kind == "hadamard":
+        return hadamard_apply(A, b, seed, d)
     if kind == "gaussian":
         return gaussian_apply(A, b, seed, d)
     raise ValueError(kind)

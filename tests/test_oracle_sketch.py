@@ -11,6 +11,10 @@ zeta matrices with one +-1 per column (built here entry by entry from the
 per-k hashes), the sparse product equals that dense product and an explicit
 loop, the hashes of different k are independent (collision rate 1/d), and
 E||Sx||^2 = zeta ||x||^2 (statistical).
+Hadamard sketch (SRHT): the popcount sign rows equal scipy.linalg.hadamard
+(Sylvester construction) entry for entry; S A equals the product built with
+scipy's full Hadamard matrix on the zero-padded, sign-flipped A; sampled rows
+are uniform and signs balanced; E||Sx||^2 = ||x||^2 (statistical).
 Gaussian table: symmetric, monotone, every entry the bfloat16 rounding of the
 normal quantile computed independently by bisection on math.erfc; bfloat16
 rounding agrees with torch's float32 -> bfloat16 conversion.
@@ -274,3 +278,50 @@ def test_sparse_sign_norm_scales_with_zeta():
         vals.append(float(np.sum(sx ** 2)))
     vals = np.array(vals)
     assert abs(vals.mean() - 4 * (x @ x)) < 5 * vals.std() / math.sqrt(len(vals))
+
+
+# ----------------------------------------------------------- hadamard ----
+
+@pytest.mark.parametrize("mp", [1, 2, 8, 64, 256])
+def test_hadamard_sign_rows_equal_sylvester(mp):
+    import scipy.linalg as sla
+    H = S.hadamard_sign_matrix(np.arange(mp), mp)
+    assert np.array_equal(H, sla.hadamard(mp).astype(np.float64))
+
+
+@pytest.mark.parametrize("m,n,d", [(1000, 7, 40), (1024, 3, 1024), (5, 2, 3), (300, 1, 64)])
+def test_hadamard_apply_equals_full_transform(m, n, d):
+    import scipy.linalg as sla
+    rng = np.random.default_rng(m + n)
+    A = rng.standard_normal((m, n))
+    b = rng.standard_normal(m)
+    SA, Sb = S.hadamard_apply(A, b, 17, d)
+    mp = S.hadamard_padded_rows(m)
+    assert mp >= m and mp < 2 * max(m, 1) + 1 and (mp & (mp - 1)) == 0
+    Ap = np.zeros((mp, n + 1))
+    Ap[:m, :n] = A
+    Ap[:m, n] = b
+    Ap[:m] *= S.hadamard_signs(17, m)[:, None]
+    full = sla.hadamard(mp).astype(np.float64) @ Ap
+    ref = full[S.hadamard_rows(17, d, mp)] / math.sqrt(d)
+    np.testing.assert_allclose(np.column_stack([SA, Sb]), ref, rtol=0, atol=1e-10)
+
+
+def test_hadamard_rows_uniform_and_signs_balanced():
+    rows = S.hadamard_rows(5, 64000, 64)
+    assert rows.min() >= 0 and rows.max() < 64
+    counts = np.bincount(rows, minlength=64)
+    assert stats.chisquare(counts).pvalue > 1e-4
+    sg = S.hadamard_signs(5, 100000).astype(np.int64)
+    assert abs(sg.mean()) < 5 / math.sqrt(100000)
+
+
+def test_hadamard_unbiased_norm():
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(200)
+    vals = []
+    for seed in range(300):
+        sx, _ = S.hadamard_apply(x[:, None], None, seed, 16)
+        vals.append(float(np.sum(sx ** 2)))
+    vals = np.array(vals)
+    assert abs(vals.mean() - x @ x) < 5 * vals.std() / math.sqrt(len(vals))

@@ -248,3 +248,13 @@ def test_sparse_sign_sap_sas_and_embedding_quality():
             sv = np.linalg.svd(q.A @ np.linalg.inv(R), compute_uv=False)
             out.append(sv.max() / sv.min())
     assert np.mean(k8) < np.mean(k1)
+
+
+def test_hadamard_sketch_solves():
+    p = dense_ill_conditioned(8192, 24, seed=19, cond=1e4)
+    xs = MT.lstsq_exact(p.A, p.b)
+    r = SV.sap_sas(p.A, p.b, "hadamard", 42, 96, 100, rtol=1e-6)
+    assert MT.metrics(p.A, p.b, r.x, xs)["RE"] <= 1e-6
+    # the SRHT is a subspace embedding: A R^-1 is well conditioned at d = 4n
+    sv = np.linalg.svd(p.A @ np.linalg.inv(r.R), compute_uv=False)
+    assert sv.max() / sv.min() < 6.0
