@@ -62,7 +62,8 @@ typedef enum { SNS_DENSE_ROWMAJOR = 0, SNS_CSR = 1 } sns_layout;
 typedef enum {
   SNS_SKETCH_COUNT = 0,       /* Clarkson-Woodruff CountSketch: one +-1 per column of S */
   SNS_SKETCH_GAUSSIAN = 1,    /* dense Gaussian sketch, bf16 inputs, fp32 accumulation */
-  SNS_SKETCH_SPARSE_SIGN = 2  /* sparse sign embedding: zeta +-1 entries per column of S */
+  SNS_SKETCH_SPARSE_SIGN = 2, /* sparse sign embedding: zeta +-1 entries per column of S */
+  SNS_SKETCH_HADAMARD = 3     /* subsampled randomized Hadamard transform */
 } sns_sketch_kind;
 
 /* A tall matrix.  Dense: values (m x n row-major, leading dimension ld).
@@ -99,7 +100,14 @@ typedef struct {
  *   where S_k uses the CountSketch rule above with counter word 2 set to k
  *   (so zeta = 1 is the CountSketch); entries +-1 without scale, and two
  *   entries of a column that land in one row add.  Dense A only; zeta in
- *   1..64 with zeta * m < 2^31.  `zeta` is ignored by the other kinds. */
+ *   1..64 with zeta * m < 2^31.  `zeta` is ignored by the other kinds.
+ * Hadamard (Sec. 1.2.1, SRHT): A is padded with zero rows to m' = 2^L >= m;
+ *   S = d^{-1/2} P H D with D = diag(s(i)), H[r, i] = (-1)^popcount(r & i),
+ *   and P selecting rows r_0 .. r_{d-1} of H D A uniformly with replacement:
+ *   s(i) = -1 iff the top bit of word (i & 3) of Philox4x32-10(counter
+ *   (i >> 2 mod 2^32, i >> 34, 0, 2)) is set; r_k = (w * m') >> 32 with w word
+ *   (k & 3) of Philox4x32-10(counter (k >> 2 mod 2^32, k >> 34, 0, 3)).  Dense
+ *   fp32/fp64 A with m <= 2^26; the workspace holds m' x (n + 1) values. */
 typedef struct {
   sns_sketch_kind kind;
   int64_t d;
@@ -203,7 +211,7 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
 
 /* One problem of a batch (sns_lstsq_batched). */
 typedef struct {
-  sns_sketch sketch;    /* CountSketch or sparse sign embedding */
+  sns_sketch sketch;    /* CountSketch or sparse sign embedding (other kinds: SNS_ERR_DTYPE) */
   sns_matrix A;         /* dense row-major */
   const void* b;        /* device, m entries of A's dtype */
   double* x;            /* device fp64[n], the answer */

@@ -19,7 +19,7 @@ STATUS_NAMES = ["SNS_OK", "SNS_ERR_INVALID_ARG", "SNS_ERR_SHAPE", "SNS_ERR_DTYPE
 SNS_ERR_QUEUE_FULL, SNS_ERR_NOT_READY = 8, 9
 SNS_F32, SNS_F64 = 0, 1
 SNS_DENSE_ROWMAJOR, SNS_CSR = 0, 1
-SNS_SKETCH_COUNT, SNS_SKETCH_GAUSSIAN, SNS_SKETCH_SPARSE_SIGN = 0, 1, 2
+SNS_SKETCH_COUNT, SNS_SKETCH_GAUSSIAN, SNS_SKETCH_SPARSE_SIGN, SNS_SKETCH_HADAMARD = 0, 1, 2, 3
 
 
 class SnsError(RuntimeError):
@@ -193,12 +193,12 @@ def csr(row_ptr, col_idx, values, m: int, n: int) -> Matrix:
 
 
 SKETCH_KINDS = {"count": SNS_SKETCH_COUNT, "gaussian": SNS_SKETCH_GAUSSIAN,
-                "sparse": SNS_SKETCH_SPARSE_SIGN}
+                "sparse": SNS_SKETCH_SPARSE_SIGN, "hadamard": SNS_SKETCH_HADAMARD}
 
 
 def sketch_desc(kind: str, d: int, seed: int, zeta: int = 1) -> Sketch:
-    """kind: "count" (CountSketch), "gaussian", or "sparse" (sparse sign
-    embedding with zeta nonzeros per column)."""
+    """kind: "count" (CountSketch), "gaussian", "sparse" (sparse sign
+    embedding with zeta nonzeros per column) or "hadamard" (SRHT)."""
     return Sketch(SKETCH_KINDS[kind], d, seed, zeta)
 
 

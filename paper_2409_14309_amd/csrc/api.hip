@@ -47,6 +47,10 @@ sns_status sns_sketch_workspace_size(const sns_sketch* sk, const sns_matrix* A, 
     *bytes = gauss_workspace_bytes(*A, (uint32_t)sk->d);
     return SNS_OK;
   }
+  if (sk->kind == SNS_SKETCH_HADAMARD) {
+    *bytes = hadamard_workspace_bytes(*A, (uint32_t)sk->d);
+    return SNS_OK;
+  }
   if (A->layout == SNS_CSR) {  // enough for either accumulator width
     *bytes = csr_workspace_bytes(*A, (uint32_t)sk->d, true);
     return SNS_OK;
@@ -77,6 +81,10 @@ sns_status sns_sketch_apply(const sns_sketch* sk, const sns_matrix* A, const voi
   if (sk->kind == SNS_SKETCH_GAUSSIAN) {
     if (ws_bytes < gauss_workspace_bytes(*A, (uint32_t)sk->d)) return SNS_ERR_OUT_OF_MEMORY;
     return launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, SA, Sb, workspace, st);
+  }
+  if (sk->kind == SNS_SKETCH_HADAMARD) {
+    if (ws_bytes < hadamard_workspace_bytes(*A, (uint32_t)sk->d)) return SNS_ERR_OUT_OF_MEMORY;
+    return launch_hadamard_sketch(*A, (uint32_t)sk->d, sk->seed, b, SA, Sb, workspace, st);
   }
   if (A->layout == SNS_CSR)
     return launch_csr_sketch(*A, (uint32_t)sk->d, sk->seed, b, SA, Sb, acc64, workspace, ws_bytes, st);
@@ -173,6 +181,8 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   if ((s = t.upload(st)) != SNS_OK) return s;
   if (sk->kind == SNS_SKETCH_GAUSSIAN)
     s = launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, w.gauss, st);
+  else if (sk->kind == SNS_SKETCH_HADAMARD)
+    s = launch_hadamard_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, w.gauss, st);
   else if (A->layout == SNS_CSR)
     s = launch_csr_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, o.accum_fp64 != 0, w.csr,
                           w.csr_bytes, st);

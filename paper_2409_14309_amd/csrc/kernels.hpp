@@ -373,6 +373,10 @@ sns_status launch_lsqr_flags(const LsqrJob& j, int* out, hipStream_t st);
 // ------------------------------------------------------------- Gaussian ----
 const uint16_t* gauss_table_host();
 size_t gauss_workspace_bytes(const sns_matrix& A, uint32_t d);
+// Hadamard sketch (SRHT): the transformed blocks B (m' x (n + 1)) and its launch.
+size_t hadamard_workspace_bytes(const sns_matrix& A, uint32_t d);
+sns_status launch_hadamard_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
+                                  void* SA, void* Sb, void* ws, hipStream_t st);
 sns_status launch_gauss_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
                                void* SA, void* Sb, void* ws, hipStream_t st);
 

@@ -29,13 +29,15 @@ sns_status check_matrix(const sns_matrix* A) {
 sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A) {
   if (!sk) return SNS_ERR_INVALID_ARG;
   if (sk->kind != SNS_SKETCH_COUNT && sk->kind != SNS_SKETCH_GAUSSIAN &&
-      sk->kind != SNS_SKETCH_SPARSE_SIGN)
+      sk->kind != SNS_SKETCH_SPARSE_SIGN && sk->kind != SNS_SKETCH_HADAMARD)
     return SNS_ERR_INVALID_ARG;
   if (sk->d < 1 || sk->d > kMaxD) return SNS_ERR_SHAPE;
   if (sk->kind == SNS_SKETCH_SPARSE_SIGN && (sk->zeta < 1 || sk->zeta > 64))
     return SNS_ERR_INVALID_ARG;
   if (A) {
     if (sk->kind == SNS_SKETCH_SPARSE_SIGN && A->layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+    if (sk->kind == SNS_SKETCH_HADAMARD && A->layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+    if (sk->kind == SNS_SKETCH_HADAMARD && A->m > kMaxHadRows) return SNS_ERR_SHAPE;
     if (sk->kind == SNS_SKETCH_SPARSE_SIGN && (int64_t)sk->zeta * A->m > kMaxRows)
       return SNS_ERR_SHAPE;
     if (sk->d < A->n || sk->d > A->m) return SNS_ERR_SHAPE;
@@ -75,7 +77,9 @@ sns_status run_sketch_jobs(const Jobs& J, hipStream_t st) {
 
 void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
                       const sns_solve_opts& o, LstsqWs& w) {
-  if (sk.kind == SNS_SKETCH_GAUSSIAN) {
+  if (sk.kind == SNS_SKETCH_HADAMARD) {
+    w.gauss = c.take<char>(hadamard_workspace_bytes(A, (uint32_t)sk.d));
+  } else if (sk.kind == SNS_SKETCH_GAUSSIAN) {
     w.gauss = c.take<char>(gauss_workspace_bytes(A, (uint32_t)sk.d));
   } else if (A.layout == SNS_CSR) {
     w.csr_bytes = csr_workspace_bytes(A, (uint32_t)sk.d, o.accum_fp64 != 0);
@@ -99,7 +103,8 @@ void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
 
 void build_lstsq_jobs(ArgTable& t, Jobs& J, const sns_sketch& sk, const sns_matrix& A,
                       const void* b, double* x, const sns_solve_opts& o, const LstsqWs& w) {
-  if (sk.kind != SNS_SKETCH_GAUSSIAN && A.layout == SNS_DENSE_ROWMAJOR)
+  if ((sk.kind == SNS_SKETCH_COUNT || sk.kind == SNS_SKETCH_SPARSE_SIGN) &&
+      A.layout == SNS_DENSE_ROWMAJOR)
     add_sketch_jobs(t, J, sk, A, b, w.SA, w.Sb, w.sw);
   const std::vector<QrArgs> qa{
       qr_args(sk.d, A.n, w.SA, A.n, w.Sb, w.q, w.q.xw, nullptr, w.info)};
@@ -206,7 +211,9 @@ sns_status check_batch(const sns_problem* P, int count) {
     sns_status s = check_matrix(&q.A);
     if (s != SNS_OK) return s;
     if ((s = check_sketch(&q.sketch, &q.A)) != SNS_OK) return s;
-    if (q.sketch.kind == SNS_SKETCH_GAUSSIAN || q.A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
+    if ((q.sketch.kind != SNS_SKETCH_COUNT && q.sketch.kind != SNS_SKETCH_SPARSE_SIGN) ||
+        q.A.layout != SNS_DENSE_ROWMAJOR)
+      return SNS_ERR_DTYPE;
     if (q.A.dtype != P[0].A.dtype) return SNS_ERR_DTYPE;
     if (q.opts.refine == 2) return SNS_ERR_INVALID_ARG;  // SAA-SAS: single-problem calls only
     if ((s = check_solve(q.sketch, q.A, q.opts)) != SNS_OK) return s;

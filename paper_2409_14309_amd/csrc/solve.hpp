@@ -13,6 +13,7 @@ constexpr int64_t kMaxRows = (int64_t(1) << 31) - 1;  // row ids fit 31 bits
 constexpr int64_t kMaxD = 16384;      // CountSketch bucket sort (LDS histograms)
 constexpr int64_t kMaxQrD = 8192;     // register-resident QR panels
 constexpr int64_t kMaxCsrN = 4096;    // CSR sketch: one output row per wave in LDS
+constexpr int64_t kMaxHadRows = int64_t(1) << 26;  // SRHT: pass 2 reads d 2^(L-10) rows
 
 sns_status check_matrix(const sns_matrix* A);
 sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A);
@@ -56,7 +57,7 @@ size_t table_bytes(F&& build) {
 
 struct LstsqWs {
   SketchWs sw;
-  void* gauss = nullptr;  // Gaussian sketch partials
+  void* gauss = nullptr;  // Gaussian sketch partials or the Hadamard sketch's blocks
   void* csr = nullptr;    // CSR sketch workspace
   size_t csr_bytes = 0;
   void* SA = nullptr;
