@@ -300,6 +300,8 @@ def main():
                     help="CountSketch workloads: > 1 uses the sparse sign embedding with zeta "
                          "nonzeros per column")
     ap.add_argument("--d", type=int, default=0, help="override the workload's sketch size")
+    ap.add_argument("--sketch", default="", choices=["", "count", "gaussian", "hadamard"],
+                    help="override the workload's sketch operator")
     ap.add_argument("--solver", default="sap", choices=["sap", "saa"],
                     help="refinement: SAP-SAS (LSQR on A R^-1 applied implicitly) or SAA-SAS "
                          "(Y = A R^-1 formed once, LSQR on Y)")
@@ -332,9 +334,11 @@ def main():
     if args.d:
         d = args.d
     zeta = 1
+    if args.sketch:
+        kind = args.sketch
     if args.zeta > 1 and kind == "count":
         kind, zeta = "sparse", args.zeta
-    seed = 1001 if kind != "gaussian" else 1003
+    seed = 1003 if gen == "dense_scaled_columns" else 1001
     dev = torch.device("cuda:0")
     paper = gen == "paper_benchmark_device"
     t0 = time.time()
@@ -410,6 +414,15 @@ def main():
     }
     # Gaussian sketch: 2 d m n flops for G A plus 2 d m for G b
     flops_per = {"gauss_mfma": 2.0 * d * m * n + 2.0 * d * m}
+    # Hadamard sketch: the first butterfly pass reads [A | b] and writes the
+    # m' x (n + 1) buffer, each later pass reads and writes it, the sampled
+    # rows read d 2^(L - 8 P) rows of it
+    L = max(0, (m - 1).bit_length())
+    mp = 1 << L
+    P = max(1, (L + 7) // 8 - 1)
+    bytes_per["srht_pass1"] = es * m * (n + 1) + es * mp * (n + 1)
+    bytes_per["srht_pass"] = 2.0 * es * mp * (n + 1)
+    bytes_per["srht_sample"] = es * d * (1 << (L - min(L, 8 * P))) * (n + 1) + es * d * (n + 1)
     # SAA-SAS: Y = A R^-1 with R^-1 upper triangular, n (n + 1) / 2 fp64
     # multiply-adds per row of A, on the vector ALUs
     alu_flops_per = {"form_y": float(m) * n * (n + 1)}
@@ -420,7 +433,8 @@ def main():
             ach = bytes_per[kname] / (avg_us * 1e-6) / 1e9
             return {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
-                    "traffic": measured_traffic(kname, kernel_source_hash(*KERNEL_SOURCES[kname])),
+                    "traffic": (measured_traffic(kname, kernel_source_hash(*KERNEL_SOURCES[kname]))
+                                if kname in KERNEL_SOURCES else None),
                     "bytes_per_launch": bytes_per[kname], "avg_launch_us": avg_us, "launches": cnt}
         if kname in flops_per:
             ach = flops_per[kname] / (avg_us * 1e-6) / 1e12
@@ -451,6 +465,7 @@ def main():
                        "GBps_with_sort": round(bytes_per["cs_gather"] / ((cs[2] + sort_us) * 1e-6) / 1e9, 1)}
 
     form_y = roofline("form_y") if "form_y" in kt else None
+    hadamard = {k: roofline(k) for k in ("srht_pass1", "srht_pass", "srht_sample") if k in kt} or None
     accuracy = None
     if x_exact is not None:
         # x_exact is the least-squares solution and beta the optimal residual
@@ -487,7 +502,7 @@ def main():
         "data": data_desc,
         "config": {"workload": args.workload, "m": m, "n": n, "d": d,
                    "sketch": {"count": "countsketch", "gaussian": "gaussian",
-                              "sparse": f"sparse sign (zeta {zeta})"}[kind],
+                              "sparse": f"sparse sign (zeta {zeta})", "hadamard": "SRHT"}[kind],
                    "solver": ("SAA-SAS (sketch, Householder QR, Y = A R^-1 formed, LSQR on Y)"
                               if refine == 2 else
                               "SAP-SAS (sketch, Householder QR, LSQR on A R^-1)"),
@@ -500,6 +515,7 @@ def main():
         "countsketch": countsketch,
         "gaussian_sketch": gauss,
         "form_y": form_y,
+        "hadamard_sketch": hadamard,
         "accuracy": accuracy,
         "roofline": roof,
         "kernels": {k: {"launches": v[0], "total_ms": round(v[1], 4), "avg_us": round(v[2], 3)}

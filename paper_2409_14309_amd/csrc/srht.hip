@@ -8,14 +8,19 @@
 //   r_k  = (w * m') >> 32, w word (k & 3) of Philox4x32-10 at counter
 //         (k >> 2 mod 2^32, k >> 34, 0, 3); key = seed.
 //
-// H = H_top (x) H_low splits the row index i = (i_top, i_low) with i_low
-// the low b = min(L, 10) bits.  Pass 1 (k_srht_block) transforms each block
-// of 2^b consecutive rows of D [A | b] in LDS (b butterfly stages) and writes
-// the result B (m' x C, A's dtype, C = n + 1 with b).  Pass 2
-// (k_srht_sample) forms each sampled row r = (r_top, r_low) as
-// sum over i_top of (-1)^popcount(r_top & i_top) B[(i_top, r_low)], in fp64,
-// and scales by d^{-1/2}.  Bytes: pass 1 reads A and writes B, pass 2 reads
-// d 2^(L-b) rows of B (about all of B once when d ~ 2^b).
+// H is the Kronecker product of 2 x 2 factors, one per bit of the row index,
+// so the transform is a sequence of butterfly stages, one per bit, in any
+// order.  Full passes (k_srht_pass) each apply the stages of up to 8
+// consecutive bits [lo, lo + nb): a work-group loads the 2^nb rows that differ
+// only in those bits (row segments of 32 columns: 128 bytes fp32, 256 fp64),
+// applies the stages in registers and one LDS exchange, and writes the result
+// back in place of the same rows (pass 1 reads D [A | b], zero-padded; later
+// passes ping-pong between two m' x C buffers, C = n + 1 with b).  The last
+// at most 8 bits are never transformed in full: each sampled row r is formed
+// directly (k_srht_sample) as the sum over the top index i_top of
+// (-1)^popcount(r_top & i_top) B[(i_top, r_low)], in fp64, scaled by d^{-1/2}.
+// Bytes for m' = 2^L rows: ceil(L / 8) - 1 full passes (at least one), each
+// reading and writing m' x C values, plus d 2^(L - 8 P) rows for the samples.
 #include <math.h>
 
 #include "common.hpp"
@@ -26,7 +31,6 @@ namespace sns {
 namespace {
 
 constexpr int kHThreads = 256;
-constexpr int kHBlockBits = 10;
 
 __device__ __forceinline__ uint32_t had_word(uint64_t seed, uint64_t idx, uint32_t tag) {
   const uint64_t q = idx >> 2;
@@ -40,47 +44,90 @@ __device__ __forceinline__ uint32_t had_word(uint64_t seed, uint64_t idx, uint32
   }
 }
 
-// One block of BR = 2^bits rows x CW columns of D [A | b]: load (signs,
-// zero rows past m), `bits` butterfly stages in LDS, store to B.
-template <typename T, int CW>
-__global__ __launch_bounds__(kHThreads) void k_srht_block(const T* __restrict__ A, int64_t ld,
-                                                          int64_t m, int n, const T* __restrict__ b,
-                                                          uint64_t seed, int bits, int ctiles,
-                                                          T* __restrict__ B, int C) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  T* tile = reinterpret_cast<T*>(smem);  // [BR][CW]
-  const int BR = 1 << bits;
-  const int t = threadIdx.x;
+// One full pass over the bits [lo, lo + NB): work-group (o, ct) transforms
+// the 2^NB rows row(j) = (o mod 2^lo) + (j << lo) + ((o >> lo) << (lo + NB))
+// over columns [CW ct, CW ct + CW).  Thread (g, c), g < RT, holds j = g + RT k
+// and applies the stages of the bits of k in registers; one LDS exchange
+// (row stride CW + 1) then gives each thread groups of RT consecutive j for
+// the stages of the bits of g.  src == nullptr: the first pass, reading
+// D [A | b] (rows past m are zero).
+template <typename T, int CW, int NB>
+__global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ src,
+                                                         const T* __restrict__ A, int64_t ld,
+                                                         int64_t m, int n, const T* __restrict__ b,
+                                                         uint64_t seed, int lo, int ctiles,
+                                                         T* __restrict__ dst, int C) {
+  constexpr int BR = 1 << NB;
+  constexpr int RT0 = kHThreads / CW;
+  constexpr int RT = RT0 < BR ? RT0 : BR, NV = BR / RT, LDT = CW + 1;
+  __shared__ T tile[BR * LDT];
+  __shared__ unsigned char neg[BR];  // first pass: sign bits of the block's rows
+  const int t = threadIdx.x, g = t / CW, c = t % CW;
   const int ct = (int)(blockIdx.x % (unsigned)ctiles);
-  const int64_t blk = blockIdx.x / (unsigned)ctiles;
-  const int c0 = ct * CW;
-  const int64_t i0 = blk << bits;
-  for (int e = t; e < BR * CW; e += kHThreads) {
-    const int r = e / CW, c = e % CW, col = c0 + c;
-    const int64_t i = i0 + r;
-    T v = T(0);
-    if (i < m && col <= n) {
-      if (col < n) v = A[i * ld + col];
-      else if (b) v = b[i];
-      if ((had_word(seed, (uint64_t)i, 2u) >> 31) != 0u) v = -v;
-    }
-    tile[e] = v;
-  }
-  __syncthreads();
-  for (int s = 0; s < bits; ++s) {
-    const int h = 1 << s;
-    for (int q = t; q < (BR / 2) * CW; q += kHThreads) {
-      const int c = q % CW, p = q / CW;
-      const int r = ((p >> s) << (s + 1)) | (p & (h - 1));
-      const T x = tile[r * CW + c], y = tile[(r + h) * CW + c];
-      tile[r * CW + c] = x + y;
-      tile[(r + h) * CW + c] = x - y;
-    }
+  const int64_t o = blockIdx.x / (unsigned)ctiles;
+  const int64_t olow = o & ((int64_t(1) << lo) - 1), ohigh = o >> lo;
+  auto row = [&](int j) -> int64_t { return olow + ((int64_t)j << lo) + (ohigh << (lo + NB)); };
+  const int col = ct * CW + c;
+  const bool active = g < RT;
+  if (!src) {  // lo = 0: the block's rows are consecutive, one Philox call per 4 rows
+    for (int j = t; j < BR; j += kHThreads) neg[j] = (unsigned char)(had_word(seed, (uint64_t)row(j), 2u) >> 31);
     __syncthreads();
   }
-  for (int e = t; e < BR * CW; e += kHThreads) {
-    const int r = e / CW, c = e % CW, col = c0 + c;
-    if (col < C) B[(i0 + r) * C + col] = tile[e];
+  T v[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    T x = T(0);
+    if (active) {
+      const int64_t i = row(g + RT * k);
+      if (src) {
+        if (col < C) x = src[i * C + col];
+      } else if (i < m && col <= n) {
+        if (col < n) x = A[i * ld + col];
+        else if (b) x = b[i];
+        if (neg[g + RT * k]) x = -x;
+      }
+    }
+    v[k] = x;
+  }
+#pragma unroll
+  for (int h = 1; h < NV; h <<= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+      if ((k & h) == 0) {
+        const T x = v[k], y = v[k + h];
+        v[k] = x + y;
+        v[k + h] = x - y;
+      }
+  if constexpr (RT == 1) {
+    if (active && col < C) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) dst[row(k) * C + col] = v[k];
+    }
+  } else {
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) tile[(g + RT * k) * LDT + c] = v[k];
+    }
+    __syncthreads();
+    for (int q = t; q < NV * CW; q += kHThreads) {
+      const int grp = q / CW, cc = q % CW, ccol = ct * CW + cc;
+      T w[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) w[r] = tile[(grp * RT + r) * LDT + cc];
+#pragma unroll
+      for (int h = 1; h < RT; h <<= 1)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+          if ((r & h) == 0) {
+            const T x = w[r], y = w[r + h];
+            w[r] = x + y;
+            w[r + h] = x - y;
+          }
+      if (ccol < C) {
+#pragma unroll
+        for (int r = 0; r < RT; ++r) dst[row(grp * RT + r) * C + ccol] = w[r];
+      }
+    }
   }
 }
 
@@ -124,7 +171,7 @@ __global__ __launch_bounds__(kHThreads) void k_srht_sample(const T* __restrict__
 }
 
 struct HadPlan {
-  int L, bits, C;
+  int L, P, C;  // m' = 2^L rows, P full passes over bits [0, 8 P) (the last may be shorter)
   uint64_t mp;
 };
 
@@ -133,26 +180,52 @@ HadPlan had_plan(const sns_matrix& A, bool with_b) {
   p.L = 0;
   while ((int64_t(1) << p.L) < A.m) ++p.L;
   p.mp = uint64_t(1) << p.L;
-  p.bits = p.L < kHBlockBits ? p.L : kHBlockBits;
+  p.P = (p.L + 7) / 8 - 1;
+  if (p.P < 1) p.P = 1;
   p.C = (int)A.n + (with_b ? 1 : 0);
   return p;
+}
+
+template <typename T, int CW, int NB>
+void launch_pass(dim3 grid, hipStream_t st, const T* src, const sns_matrix& A, const void* b,
+                 uint64_t seed, int lo, int ctiles, T* dst, int C) {
+  SNS_LAUNCH(src ? "srht_pass" : "srht_pass1", (k_srht_pass<T, CW, NB>), grid, dim3(kHThreads), 0, st, src,
+             static_cast<const T*>(A.values), A.ld, A.m, (int)A.n, static_cast<const T*>(b), seed,
+             lo, ctiles, dst, C);
 }
 
 template <typename T, int CW>
 sns_status launch_had(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b, void* SA,
                       void* Sb, void* ws, hipStream_t st) {
   const HadPlan p = had_plan(A, b != nullptr);
-  T* B = static_cast<T*>(ws);
+  const size_t buf = align_up((size_t)p.mp * (A.n + 1) * sizeof(T));
+  T* Bs[2] = {static_cast<T*>(ws), reinterpret_cast<T*>(static_cast<char*>(ws) + buf)};
   const int ctiles = (p.C + CW - 1) / CW;
-  const uint64_t blocks = (p.mp >> p.bits) * (uint64_t)ctiles;
-  if (blocks > 0x7FFFFFFFull) return SNS_ERR_SHAPE;
-  const size_t lds = ((size_t)1 << p.bits) * CW * sizeof(T);
-  SNS_LAUNCH("srht_block", (k_srht_block<T, CW>), dim3((unsigned)blocks), dim3(kHThreads), lds, st,
-             static_cast<const T*>(A.values), A.ld, A.m, (int)A.n, static_cast<const T*>(b), seed,
-             p.bits, ctiles, B, p.C);
+  const T* src = nullptr;
+  int lo = 0;
+  for (int q = 0; q < p.P; ++q) {
+    const int nb = (p.L - lo) < 8 ? (p.L - lo) : 8;
+    T* dst = Bs[q & 1];
+    const uint64_t blocks = (p.mp >> nb) * (uint64_t)ctiles;
+    if (blocks > 0x7FFFFFFFull) return SNS_ERR_SHAPE;
+    const dim3 grid((unsigned)blocks);
+    switch (nb) {
+      case 0: launch_pass<T, CW, 0>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 1: launch_pass<T, CW, 1>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 2: launch_pass<T, CW, 2>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 3: launch_pass<T, CW, 3>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 4: launch_pass<T, CW, 4>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 5: launch_pass<T, CW, 5>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 6: launch_pass<T, CW, 6>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 7: launch_pass<T, CW, 7>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      default: launch_pass<T, CW, 8>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+    }
+    src = dst;
+    lo += nb;
+  }
   const int stiles = (p.C + kHThreads - 1) / kHThreads;
   SNS_LAUNCH("srht_sample", k_srht_sample<T>, dim3((unsigned)(d * (uint64_t)stiles)),
-             dim3(kHThreads), 0, st, (const T*)B, p.C, p.bits, p.L, seed, stiles, (int)A.n,
+             dim3(kHThreads), 0, st, src, p.C, lo, p.L, seed, stiles, (int)A.n,
              1.0 / sqrt((double)d), static_cast<T*>(SA), static_cast<T*>(Sb));
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
@@ -162,14 +235,15 @@ sns_status launch_had(const sns_matrix& A, uint32_t d, uint64_t seed, const void
 
 size_t hadamard_workspace_bytes(const sns_matrix& A, uint32_t /*d*/) {
   const HadPlan p = had_plan(A, true);
-  return align_up((size_t)p.mp * p.C * (A.dtype == SNS_F64 ? 8 : 4));
+  const size_t buf = align_up((size_t)p.mp * p.C * (A.dtype == SNS_F64 ? 8 : 4));
+  return p.P > 1 ? 2 * buf : buf;
 }
 
 sns_status launch_hadamard_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
                                   void* SA, void* Sb, void* ws, hipStream_t st) {
   if (A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
-  if (A.dtype == SNS_F64) return launch_had<double, 8>(A, d, seed, b, SA, Sb, ws, st);
-  return launch_had<float, 16>(A, d, seed, b, SA, Sb, ws, st);
+  if (A.dtype == SNS_F64) return launch_had<double, 32>(A, d, seed, b, SA, Sb, ws, st);
+  return launch_had<float, 32>(A, d, seed, b, SA, Sb, ws, st);
 }
 
 }  // namespace sns
