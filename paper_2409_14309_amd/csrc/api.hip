@@ -154,6 +154,7 @@ sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
   if ((s = check_sketch(sk, A)) != SNS_OK) return s;
   if (!bytes) return SNS_ERR_INVALID_ARG;
   const sns_solve_opts o = opts ? *opts : default_opts();
+  if ((s = check_solve(*sk, *A, o)) != SNS_OK) return s;
   Carve c(nullptr, 0);
   LstsqWs w;
   carve_lstsq(c, *sk, *A, o, w);

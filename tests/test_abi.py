@@ -81,6 +81,35 @@ def test_host_side_argument_checks():
     assert lib.sns_qr_solve(10, 20, 0, C.c_void_p(fake), 20, C.c_void_p(fake), C.c_void_p(fake),
                             None, None, C.c_void_p(fake), 1 << 30, None) == 2
     assert lib.sns_hash(1, 0, 0, 10, C.c_void_p(fake), None, None) == 2
+    # sparse sign embedding: zeta in 1..64, dense only, zeta * m < 2^31
+    Ad = sns.Matrix(1000, 10, 0, 0, fake, 10, None, None, 0)
+    for z, want in ((0, 1), (65, 1), (64, 0), (1, 0)):
+        ss = sns.Sketch(2, 64, 1, z)
+        assert lib.sns_sketch_workspace_size(C.byref(ss), C.byref(Ad), C.byref(nb)) == want
+    assert lib.sns_sketch_workspace_size(C.byref(sns.Sketch(2, 64, 1, 4)), C.byref(Ac),
+                                         C.byref(nb)) == 3
+    Abig = sns.Matrix((1 << 31) - 1, 10, 0, 0, fake, 10, None, None, 0)
+    assert lib.sns_sketch_workspace_size(C.byref(sns.Sketch(2, 64, 1, 2)), C.byref(Abig),
+                                         C.byref(nb)) == 2
+    # Hadamard sketch: dense only, m <= 2^26; workspace holds the m' x (n + 1) buffers
+    sh = sns.Sketch(3, 64, 1, 0)
+    assert lib.sns_sketch_workspace_size(C.byref(sh), C.byref(Ad), C.byref(nb)) == 0
+    assert nb.value >= 1024 * 11 * 4
+    assert lib.sns_sketch_workspace_size(C.byref(sh), C.byref(Ac), C.byref(nb)) == 3
+    Ahuge = sns.Matrix((1 << 26) + 1, 10, 0, 0, fake, 10, None, None, 0)
+    assert lib.sns_sketch_workspace_size(C.byref(sh), C.byref(Ahuge), C.byref(nb)) == 2
+    # refine outside 0..2; SAA-SAS and non-sparse sketches are rejected by batches
+    Aa = sns.Matrix(1000, 10, 0, 0, fake, 12, None, None, 0)  # 16-byte rows for refinement
+    o3 = sns.opts(refine=3, max_iters=5)
+    assert lib.sns_lstsq_workspace_size(C.byref(sk), C.byref(Aa), C.byref(o3), C.byref(nb)) == 1
+    o2 = sns.opts(refine=2, max_iters=5)
+    assert lib.sns_lstsq_workspace_size(C.byref(sk), C.byref(Aa), C.byref(o2), C.byref(nb)) == 0
+    assert nb.value >= 1000 * 12 * 4  # holds Y
+    assert lib.sns_lstsq_workspace_size(C.byref(sk), C.byref(Ad), C.byref(o2), C.byref(nb)) == 2
+    probs = (sns.Problem * 1)(sns.Problem(sk, Aa, fake, fake, o2))
+    assert lib.sns_lstsq_batched_workspace_size(probs, 1, C.byref(nb)) == 1
+    probs = (sns.Problem * 1)(sns.Problem(sh, Aa, fake, fake, sns.opts(refine=1, max_iters=5)))
+    assert lib.sns_lstsq_batched_workspace_size(probs, 1, C.byref(nb)) == 3
 
 
 def test_device_gaussian_table_matches_oracle_bits():
