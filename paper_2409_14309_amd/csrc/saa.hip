@@ -7,12 +7,9 @@
 // triangular X (n x n, row-major fp64, zeros below the diagonal).  Products
 // and sums are fp64 (A's values are widened exactly); Y is stored in A's
 // dtype with row stride ldy.  Work-group tile: 128 rows x 128 columns of Y,
-// K-steps of 16 rows of X; a column tile starting at j0 only needs the rows
-// k < j0 + 128 of X (X is upper triangular), so the product costs about
-// m n^2 multiply-adds.  Each thread owns an 8 x 8 block of the tile: rows
-// 2 ty + 32 c + e and columns 2 tx + 32 c' + e' (c, c' in 0..3, e, e' in
-// 0..1), so its LDS reads are 16-byte pairs that a wave's lanes take from
-// consecutive addresses.
+// K-steps of 16 rows of X staged in LDS; a column tile starting at j0 only
+// needs the rows k < j0 + 128 of X (X is upper triangular), so the product
+// costs about m n^2 multiply-adds, taken on the fp64 matrix cores.
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -23,11 +20,11 @@ namespace {
 constexpr int kYT = 128, kYK = 16, kYThreads = 256, kYPad = 2;
 
 template <typename T>
-__global__ __launch_bounds__(kYThreads) void k_form_y(const T* __restrict__ A, int64_t ld,
+__global__ __launch_bounds__(kYThreads, 2) void k_form_y(const T* __restrict__ A, int64_t ld,
                                                       int64_t m, int n,
                                                       const double* __restrict__ X,
                                                       T* __restrict__ Y, int64_t ldy, int ctn) {
-  __shared__ __attribute__((aligned(16))) double As[kYK][kYT + kYPad];
+  __shared__ __attribute__((aligned(16))) T As[kYK][kYT + kYPad];  // A's dtype, widened when read
   __shared__ __attribute__((aligned(16))) double Xs[kYK][kYT + kYPad];
   const int t = threadIdx.x;
   const int cj = (int)(blockIdx.x % (unsigned)ctn);
@@ -42,7 +39,8 @@ __global__ __launch_bounds__(kYThreads) void k_form_y(const T* __restrict__ A, i
   const T* arow = A + (ai < m ? ai : 0) * ld;
   // X loader: row xk of the step, columns 8 xq .. 8 xq + 7 of the tile
   const int xk = t >> 4, xq = t & 15;
-  double ra[8], rx[8];
+  T ra[8];
+  double rx[8];
   auto load = [&](int k0) {
     const int ka = k0 + 8 * ah;
     if (ai < m && ka + 8 <= n) {
@@ -50,19 +48,19 @@ __global__ __launch_bounds__(kYThreads) void k_form_y(const T* __restrict__ A, i
 #pragma unroll
         for (int e = 0; e < 8; e += 2) {
           const double2 v = *reinterpret_cast<const double2*>(arow + ka + e);
-          ra[e] = v.x;
-          ra[e + 1] = v.y;
+          ra[e] = (T)v.x;
+          ra[e + 1] = (T)v.y;
         }
       } else {
 #pragma unroll
         for (int e = 0; e < 8; e += 4) {
           const float4 v = *reinterpret_cast<const float4*>(arow + ka + e);
-          ra[e] = v.x; ra[e + 1] = v.y; ra[e + 2] = v.z; ra[e + 3] = v.w;
+          ra[e] = (T)v.x; ra[e + 1] = (T)v.y; ra[e + 2] = (T)v.z; ra[e + 3] = (T)v.w;
         }
       }
     } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) ra[e] = (ai < m && ka + e < n) ? (double)arow[ka + e] : 0.0;
+      for (int e = 0; e < 8; ++e) ra[e] = (ai < m && ka + e < n) ? arow[ka + e] : T(0);
     }
     const int kx = k0 + xk;
     const double* xrow = X + (int64_t)(kx < n ? kx : 0) * n;
@@ -79,12 +77,20 @@ __global__ __launch_bounds__(kYThreads) void k_form_y(const T* __restrict__ A, i
     for (int e = 0; e < 8; ++e) Xs[xk][8 * xq + e] = rx[e];
   };
 
-  const int ty = t >> 4, tx = t & 15;
-  double acc[8][8];
+  // products on the matrix cores: wave (wr, wc) owns rows [64 wr, 64 wr + 64)
+  // and columns [64 wc, 64 wc + 64) of the tile as 4 x 4 tiles of 16 x 16,
+  // each v_mfma_f64_16x16x4f64 adding 4 K-rows: lane l supplies
+  // A[16 rt + l % 16][k + l / 16] and X[k + l / 16][16 ct + l % 16].
+  typedef __attribute__((__vector_size__(4 * sizeof(double)))) double f64x4;
+  const int lane = t & 63, wave = t >> 6, wr = wave >> 1, wc = wave & 1;
+  const int li = lane & 15, lk = lane >> 4;
+  f64x4 acc[4][4];
 #pragma unroll
-  for (int r = 0; r < 8; ++r)
+  for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[r][c] = 0.0;
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[rt][ct][q] = 0.0;
 
   load(0);
   for (int kb = 0; kb < nk; ++kb) {
@@ -92,35 +98,34 @@ __global__ __launch_bounds__(kYThreads) void k_form_y(const T* __restrict__ A, i
     store();
     __syncthreads();
     if (kb + 1 < nk) load((kb + 1) * kYK);  // in flight during the products
-#pragma unroll 4
-    for (int k = 0; k < kYK; ++k) {
-      double a[8], x[8];
+#pragma unroll
+    for (int k4 = 0; k4 < kYK; k4 += 4) {
+      double a[4], x[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = (double)As[k4 + lk][64 * wr + 16 * r + li];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[c] = Xs[k4 + lk][64 * wc + 16 * c + li];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r], x[c], acc[r][c], 0, 0, 0);
+    }
+  }
+  // accumulator element q of lane l in a 16 x 16 fp64 tile: row l / 16 + 4 q, column l % 16
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = i0 + 64 * wr + 16 * r + lk + 4 * q;
+      if (i >= m) continue;
+      T* yrow = Y + i * ldy;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const double2 va = *reinterpret_cast<const double2*>(&As[k][2 * ty + 32 * c]);
-        const double2 vx = *reinterpret_cast<const double2*>(&Xs[k][2 * tx + 32 * c]);
-        a[2 * c] = va.x;
-        a[2 * c + 1] = va.y;
-        x[2 * c] = vx.x;
-        x[2 * c + 1] = vx.y;
+        const int j = j0 + 64 * wc + 16 * c + li;
+        if (j < n) yrow[j] = (T)acc[r][c][q];
       }
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc[r][c] = fma(a[r], x[c], acc[r][c]);
     }
-  }
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int64_t i = i0 + 2 * ty + 32 * (r >> 1) + (r & 1);
-    if (i >= m) continue;
-    T* yrow = Y + i * ldy;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int j = j0 + 2 * tx + 32 * (c >> 1) + (c & 1);
-      if (j < n) yrow[j] = (T)acc[r][c];
-    }
-  }
 }
 
 }  // namespace
