@@ -15,9 +15,10 @@
 // only in those bits (row segments of 32 columns: 128 bytes fp32, 256 fp64),
 // applies the stages in registers and one LDS exchange, and writes the result
 // back in place of the same rows (pass 1 reads D [A | b], zero-padded; later
-// passes ping-pong between two m' x C buffers, C = n + 1 with b).  The last
-// at most 8 bits are never transformed in full: each sampled row r is formed
-// directly (k_srht_sample) as the sum over the top index i_top of
+// passes ping-pong between two m' x C buffers, C = n + 1 with b, rows padded
+// to 32 values so that every segment is aligned).  The last at most 8 bits
+// are never transformed in full: each sampled row r is formed directly
+// (k_srht_sample) as the sum over the top index i_top of
 // (-1)^popcount(r_top & i_top) B[(i_top, r_low)], in fp64, scaled by d^{-1/2}.
 // Bytes for m' = 2^L rows: ceil(L / 8) - 1 full passes (at least one), each
 // reading and writing m' x C values, plus d 2^(L - 8 P) rows for the samples.
@@ -56,7 +57,8 @@ __global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ s
                                                          const T* __restrict__ A, int64_t ld,
                                                          int64_t m, int n, const T* __restrict__ b,
                                                          uint64_t seed, int lo, int ctiles,
-                                                         T* __restrict__ dst, int C) {
+                                                         T* __restrict__ dst, int C,
+                                                         int ldb) {
   constexpr int BR = 1 << NB;
   constexpr int RT0 = kHThreads / CW;
   constexpr int RT = RT0 < BR ? RT0 : BR, NV = BR / RT, LDT = CW + 1;
@@ -73,21 +75,32 @@ __global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ s
     for (int j = t; j < BR; j += kHThreads) neg[j] = (unsigned char)(had_word(seed, (uint64_t)row(j), 2u) >> 31);
     __syncthreads();
   }
+  // Loads: the common cases have no branch inside the loop, so every load of
+  // the block is in flight before the first use.
   T v[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    T x = T(0);
-    if (active) {
-      const int64_t i = row(g + RT * k);
-      if (src) {
-        if (col < C) x = src[i * C + col];
-      } else if (i < m && col <= n) {
-        if (col < n) x = A[i * ld + col];
-        else if (b) x = b[i];
-        if (neg[g + RT * k]) x = -x;
+  for (int k = 0; k < NV; ++k) v[k] = T(0);
+  if (active) {
+    if (src) {
+      if (col < C) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = src[row(g + RT * k) * ldb + col];
       }
+    } else {
+      const bool full = row(BR - 1) < m;  // the first pass reads consecutive rows
+      if (full && col < n) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = A[row(g + RT * k) * ld + col];
+      } else if (col <= n) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          const int64_t i = row(g + RT * k);
+          if (i < m) v[k] = col < n ? A[i * ld + col] : (b ? b[i] : T(0));
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NV; ++k) v[k] = neg[g + RT * k] ? -v[k] : v[k];
     }
-    v[k] = x;
   }
 #pragma unroll
   for (int h = 1; h < NV; h <<= 1)
@@ -101,7 +114,7 @@ __global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ s
   if constexpr (RT == 1) {
     if (active && col < C) {
 #pragma unroll
-      for (int k = 0; k < NV; ++k) dst[row(k) * C + col] = v[k];
+      for (int k = 0; k < NV; ++k) dst[row(k) * ldb + col] = v[k];
     }
   } else {
     if (active) {
@@ -125,7 +138,7 @@ __global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ s
           }
       if (ccol < C) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) dst[row(grp * RT + r) * C + ccol] = w[r];
+        for (int r = 0; r < RT; ++r) dst[row(grp * RT + r) * ldb + ccol] = w[r];
       }
     }
   }
@@ -135,7 +148,7 @@ __global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ s
 // (-1)^popcount(r_top & i_top) B[(i_top << bits) | r_low], eight running fp64
 // sums per thread combined in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(kHThreads) void k_srht_sample(const T* __restrict__ B, int C,
+__global__ __launch_bounds__(kHThreads) void k_srht_sample(const T* __restrict__ B, int C, int ldb,
                                                            int bits, int L, uint64_t seed,
                                                            int ctiles, int n, double scale,
                                                            T* __restrict__ SA, T* __restrict__ Sb) {
@@ -154,7 +167,7 @@ __global__ __launch_bounds__(kHThreads) void k_srht_sample(const T* __restrict__
   for (; it + 8 <= ntop; it += 8) {
     T v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = B[(((it + j) << bits) | rlow) * C + col];
+    for (int j = 0; j < 8; ++j) v[j] = B[(((it + j) << bits) | rlow) * ldb + col];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const double x = (double)v[j];
@@ -162,7 +175,7 @@ __global__ __launch_bounds__(kHThreads) void k_srht_sample(const T* __restrict__
     }
   }
   for (int j = 0; it < ntop; ++it, ++j) {
-    const double x = (double)B[((it << bits) | rlow) * C + col];
+    const double x = (double)B[((it << bits) | rlow) * ldb + col];
     acc[j] += (__popcll(rtop & (uint64_t)it) & 1) ? -x : x;
   }
   const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
@@ -171,7 +184,7 @@ __global__ __launch_bounds__(kHThreads) void k_srht_sample(const T* __restrict__
 }
 
 struct HadPlan {
-  int L, P, C;  // m' = 2^L rows, P full passes over bits [0, 8 P) (the last may be shorter)
+  int L, P, C, ldb;  // m' = 2^L rows, P full passes over bits [0, 8 P) (the last may be shorter)
   uint64_t mp;
 };
 
@@ -183,22 +196,23 @@ HadPlan had_plan(const sns_matrix& A, bool with_b) {
   p.P = (p.L + 7) / 8 - 1;
   if (p.P < 1) p.P = 1;
   p.C = (int)A.n + (with_b ? 1 : 0);
+  p.ldb = (int)((A.n + 1 + 31) / 32 * 32);  // B rows start on 128-byte boundaries
   return p;
 }
 
 template <typename T, int CW, int NB>
 void launch_pass(dim3 grid, hipStream_t st, const T* src, const sns_matrix& A, const void* b,
-                 uint64_t seed, int lo, int ctiles, T* dst, int C) {
+                 uint64_t seed, int lo, int ctiles, T* dst, int C, int ldb) {
   SNS_LAUNCH(src ? "srht_pass" : "srht_pass1", (k_srht_pass<T, CW, NB>), grid, dim3(kHThreads), 0, st, src,
              static_cast<const T*>(A.values), A.ld, A.m, (int)A.n, static_cast<const T*>(b), seed,
-             lo, ctiles, dst, C);
+             lo, ctiles, dst, C, ldb);
 }
 
 template <typename T, int CW>
 sns_status launch_had(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b, void* SA,
                       void* Sb, void* ws, hipStream_t st) {
   const HadPlan p = had_plan(A, b != nullptr);
-  const size_t buf = align_up((size_t)p.mp * (A.n + 1) * sizeof(T));
+  const size_t buf = align_up((size_t)p.mp * p.ldb * sizeof(T));
   T* Bs[2] = {static_cast<T*>(ws), reinterpret_cast<T*>(static_cast<char*>(ws) + buf)};
   const int ctiles = (p.C + CW - 1) / CW;
   const T* src = nullptr;
@@ -210,22 +224,22 @@ sns_status launch_had(const sns_matrix& A, uint32_t d, uint64_t seed, const void
     if (blocks > 0x7FFFFFFFull) return SNS_ERR_SHAPE;
     const dim3 grid((unsigned)blocks);
     switch (nb) {
-      case 0: launch_pass<T, CW, 0>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      case 1: launch_pass<T, CW, 1>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      case 2: launch_pass<T, CW, 2>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      case 3: launch_pass<T, CW, 3>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      case 4: launch_pass<T, CW, 4>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      case 5: launch_pass<T, CW, 5>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      case 6: launch_pass<T, CW, 6>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      case 7: launch_pass<T, CW, 7>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
-      default: launch_pass<T, CW, 8>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C); break;
+      case 0: launch_pass<T, CW, 0>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 1: launch_pass<T, CW, 1>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 2: launch_pass<T, CW, 2>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 3: launch_pass<T, CW, 3>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 4: launch_pass<T, CW, 4>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 5: launch_pass<T, CW, 5>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 6: launch_pass<T, CW, 6>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 7: launch_pass<T, CW, 7>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      default: launch_pass<T, CW, 8>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
     }
     src = dst;
     lo += nb;
   }
   const int stiles = (p.C + kHThreads - 1) / kHThreads;
   SNS_LAUNCH("srht_sample", k_srht_sample<T>, dim3((unsigned)(d * (uint64_t)stiles)),
-             dim3(kHThreads), 0, st, src, p.C, lo, p.L, seed, stiles, (int)A.n,
+             dim3(kHThreads), 0, st, src, p.C, p.ldb, lo, p.L, seed, stiles, (int)A.n,
              1.0 / sqrt((double)d), static_cast<T*>(SA), static_cast<T*>(Sb));
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
@@ -235,7 +249,7 @@ sns_status launch_had(const sns_matrix& A, uint32_t d, uint64_t seed, const void
 
 size_t hadamard_workspace_bytes(const sns_matrix& A, uint32_t /*d*/) {
   const HadPlan p = had_plan(A, true);
-  const size_t buf = align_up((size_t)p.mp * p.C * (A.dtype == SNS_F64 ? 8 : 4));
+  const size_t buf = align_up((size_t)p.mp * p.ldb * (A.dtype == SNS_F64 ? 8 : 4));
   return p.P > 1 ? 2 * buf : buf;
 }
 
