@@ -12,7 +12,10 @@ gauss_bf16_262144x512 times the same solve with the dense Gaussian sketch
 --workload paper_fp64_1000000x1000 times the benchmark family of Sec. 3.1
 (FP64, kappa 1e10, beta 1e-10, n = 1000, d = 4000; --m picks the row count) and
 reports its residual and forward errors against the exact solution built into
-the data.  --solver saa replaces SAP-SAS by SAA-SAS (Y = A R^-1 formed once).
+the data.  --solver saa replaces SAP-SAS by SAA-SAS (Y = A R^-1 formed once);
+--zeta Z > 1 uses the sparse sign embedding instead of the CountSketch,
+--sketch hadamard the subsampled randomized Hadamard transform, --d the
+sketch size.
 
 Prints one JSON line: solves/s (value), p50/p99 step latency, the CountSketch
 pass bandwidth, a roofline record for the dominant kernel (timed with HIP

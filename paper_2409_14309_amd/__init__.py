@@ -77,14 +77,16 @@ def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine=False
 
 
 def lstsq_batched(As, bs, ds, seeds, refine: bool = True, max_iters: int = 100, rtol: float = 1e-6,
-                  use_graph: bool = True, stream=None):
-    """Solve several dense problems in one batch; returns ([x], [Info])."""
+                  use_graph: bool = True, stream=None, zeta: int = 1):
+    """Solve several dense problems in one batch (CountSketch, or the sparse
+    sign embedding with zeta > 1); returns ([x], [Info])."""
     import torch
     probs, xs = [], []
     for A, b, d, seed in zip(As, bs, ds, seeds):
         x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
         o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0)
-        probs.append(problem(sketch_desc("count", d, seed), dense(A), b, x, o))
+        sk = sketch_desc("sparse", d, seed, zeta) if zeta > 1 else sketch_desc("count", d, seed)
+        probs.append(problem(sk, dense(A), b, x, o))
         xs.append(x)
     ws = _workspace(sns_lstsq_batched_workspace_size(probs), As[0].device)
     infos = (Info * len(probs))()
@@ -96,7 +98,8 @@ def lstsq_batched(As, bs, ds, seeds, refine: bool = True, max_iters: int = 100, 
 class Server:
     """Continuous-batching solver service over a device memory pool.
 
-    submit() queues a dense CountSketch problem (device tensors A, b; the
+    submit() queues a dense CountSketch (or, with zeta > 1, sparse sign
+    embedding) problem (device tensors A, b; the
     answer goes to a new fp64 tensor) and returns a ticket; wait()/poll()
     return (x, Info) once it has completed."""
 
@@ -109,12 +112,13 @@ class Server:
         self._live = {}
 
     def submit(self, A, b, d: int, seed: int, refine: bool = True, max_iters: int = 100,
-               rtol: float = 1e-6, x=None) -> int:
+               rtol: float = 1e-6, x=None, zeta: int = 1) -> int:
         import torch
         if x is None:
             x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
         o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0)
-        t = sns_serve_submit(self.handle, problem(sketch_desc("count", d, seed), dense(A), b, x, o))
+        sk = sketch_desc("sparse", d, seed, zeta) if zeta > 1 else sketch_desc("count", d, seed)
+        t = sns_serve_submit(self.handle, problem(sk, dense(A), b, x, o))
         self._live[t] = (A, b, x)  # keep the buffers alive while the request runs
         return t
 

@@ -1,6 +1,8 @@
 // Stable counting sort of rows by CountSketch bucket (deterministic, integer
 // only).  The keys are the rows 0..m-1, or the m entries of an ascending row
-// list.  Keys are cut into wave-blocks of `rw` consecutive keys; each wave
+// list; for the sparse sign embedding with zeta nonzeros per column, key t
+// stands for hash t % zeta of row t / zeta (zeta m keys, the row id and its
+// sign land in the permutation as for the CountSketch).  Keys are cut into wave-blocks of `rw` consecutive keys; each wave
 // histograms its block in LDS, a two-level exclusive scan in bucket-major
 // order turns the per-block counts into start offsets, and each wave then
 // places its rows in ascending order, ranking equal buckets within a batch of
