@@ -15,27 +15,15 @@ namespace sns {
 
 namespace {
 
-template <typename T, int VEC>
-struct Vec;
-template <>
-struct Vec<float, 4> { using type = float4; };
-template <>
-struct Vec<float, 2> { using type = float2; };
-template <>
-struct Vec<float, 1> { using type = float; };
-template <>
-struct Vec<double, 2> { using type = double2; };
-template <>
-struct Vec<double, 1> { using type = double; };
-
+// Rows of A are read once per sketch: nontemporal loads keep the stream from
+// displacing the partial sums and permutation in the caches.
 template <typename T, int VEC>
 __device__ __forceinline__ void load_row(const T* __restrict__ p, int col, int n, T (&v)[VEC]) {
   if (col + VEC <= n) {
-    using V = typename Vec<T, VEC>::type;
-    const V x = *reinterpret_cast<const V*>(p + col);
-    const T* e = reinterpret_cast<const T*>(&x);
+    typedef T NVT __attribute__((ext_vector_type(VEC)));
+    const NVT x = __builtin_nontemporal_load(reinterpret_cast<const NVT*>(p + col));
 #pragma unroll
-    for (int q = 0; q < VEC; ++q) v[q] = e[q];
+    for (int q = 0; q < VEC; ++q) v[q] = x[q];
   } else {
 #pragma unroll
     for (int q = 0; q < VEC; ++q) v[q] = (col + q < n) ? p[col + q] : T(0);

@@ -46,20 +46,12 @@ struct LsqrState {
 
 namespace {
 
-template <typename T, int VEC>
-struct VecT;
-template <>
-struct VecT<float, 4> { using type = float4; };
-template <>
-struct VecT<float, 1> { using type = float; };
-template <>
-struct VecT<double, 2> { using type = double2; };
-template <>
-struct VecT<double, 1> { using type = double; };
 
 constexpr int kPassWaves = 4;
 constexpr int kRedSplit = 16;      // partial groups left for the step kernel
 
+// A is read once per pass: nontemporal loads keep the stream from displacing
+// u and the partial sums in the caches.
 template <typename T, int VEC, int NCH, int LPR>
 __device__ __forceinline__ void load_row_chunks(const T* __restrict__ row, int lr, int n,
                                                 T (&a)[NCH][VEC]) {
@@ -68,11 +60,10 @@ __device__ __forceinline__ void load_row_chunks(const T* __restrict__ row, int l
   for (int c = 0; c < NCH; ++c) {
     const int col = c * CW + lr * VEC;
     if (col + VEC <= n) {
-      using V = typename VecT<T, VEC>::type;
-      const V x = *reinterpret_cast<const V*>(row + col);
-      const T* xe = reinterpret_cast<const T*>(&x);
+      typedef T NVT __attribute__((ext_vector_type(VEC)));
+      const NVT x = __builtin_nontemporal_load(reinterpret_cast<const NVT*>(row + col));
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) a[c][e] = xe[e];
+      for (int e = 0; e < VEC; ++e) a[c][e] = x[e];
     } else {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) a[c][e] = (col + e < n) ? row[col + e] : T(0);
