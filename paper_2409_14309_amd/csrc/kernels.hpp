@@ -345,6 +345,7 @@ struct LsqrJob {
   uint32_t ninv = 0, nred = 0, ngemv = 0;
   int count = 0;
   int maxn = 0;
+  bool unfused = false;  // some problem has n above the fused-step limit
   struct Cls {
     LsqrPlan plan;  // lpr, nch, unroll of the class
     const LsqrArgs* args;
@@ -361,7 +362,10 @@ LsqrJob build_lsqr_job(ArgTable& t, const std::vector<LsqrProb>& p, bool f64);
 // host polling of the stop flag; several problems: `max_iters` of them,
 // finished problems skipping), the final update and the report.
 sns_status launch_lsqr_setup(const LsqrJob& j, hipStream_t st);
-sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t st);
+// ring: pinned host slots (kPollSlots of them) that a single-problem job
+// posts its stop state to after every iteration; null for none.
+struct PollSlot;
+sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t st, PollSlot* ring = nullptr);
 sns_status launch_lsqr_finish(const LsqrJob& j, hipStream_t st);
 sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipStream_t st);
 // Number of problems of the job that have not stopped, written to *out

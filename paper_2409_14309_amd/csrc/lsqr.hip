@@ -21,7 +21,10 @@
 //
 // Per iteration: k_lsqr_pass (all of A), k_lsqr_reduce (partials of A^T u'),
 // k_lsqr_xtz (y = X^T z / beta - beta v; the last work-group to finish runs
-// the scalar recurrences and the n-vector updates), k_lsqr_xv (w = X v).
+// the scalar recurrences and the n-vector updates), k_lsqr_xv (w = X v).  For
+// n <= 256 the last work-group of k_lsqr_reduce to finish runs the whole step
+// after the reduction (both n x n products, the recurrences and the updates),
+// so an iteration is two launches.
 //
 // Precision: A and the m-vector u are stored in A's dtype; every product and
 // accumulation is fp64, and all n-vectors are fp64.  Once the stop rule
@@ -41,7 +44,17 @@ struct LsqrState {
   double ratio;      // alpha_{k+1} |c_k| / sigma_hat at the last iteration
   double stop;       // rtol * sigma_hat (0: run max_iters)
   int iter, max_iters, done, status;
-  unsigned int arrived;  // work-groups of k_lsqr_xtz done (reset by the last)
+  unsigned int arrived;  // work-groups of k_lsqr_xtz (or k_lsqr_reduce) done; reset by the last
+  unsigned int steps;    // iterations launched so far, stopped ones included
+};
+
+// Stop state posted by the device into pinned host memory after every
+// iteration of a single problem, so the host can poll without a copy.
+constexpr int kPollSlots = 8;
+struct PollSlot {
+  double ratio;
+  int done;  // done and step form one 64-bit word, written at once
+  int step;  // iteration the slot describes
 };
 
 namespace {
@@ -49,6 +62,11 @@ namespace {
 
 constexpr int kPassWaves = 4;
 constexpr int kRedSplit = 16;      // partial groups left for the step kernel
+constexpr int kFuseMaxN = 256;     // n up to which k_lsqr_reduce also runs the step
+constexpr int kRedThreads = 512;  // k_lsqr_reduce work-group (8 waves)
+constexpr int kRedGroups = kRedThreads / 64;
+constexpr int kFuseParts = kRedThreads / kFuseMaxN;  // threads per column in the fused step
+static_assert(kFuseParts >= 1 && kRedGroups % 4 == 0, "combine orders below");
 
 // A is read once per pass: nontemporal loads keep the stream from displacing
 // u and the partial sums in the caches.
@@ -223,15 +241,214 @@ __global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(const LsqrArgs* _
   lsqr_pass_item<T, VEC, LPR, NCH, U>(P[pi], it - mp.off[pi], zred, nred);
 }
 
+// The stop state of the iteration just run, posted to the host ring (one
+// thread of one work-group per iteration).  The stop flag and the step number
+// travel in one 64-bit store, so the host never pairs a fresh tag with a stale
+// flag; the ratio only steers how far the host runs ahead.
+// `s` is the state as it now stands (a register copy or *st itself).
+__device__ __forceinline__ void post_state(const LsqrState& s, LsqrState* st, PollSlot* ring) {
+  const unsigned int k = s.steps;
+  st->steps = k + 1u;
+  PollSlot* h = ring + k % kPollSlots;
+  h->ratio = s.ratio;
+  const unsigned long long tag =
+      ((unsigned long long)k << 32) | (unsigned long long)(unsigned int)s.done;
+  *reinterpret_cast<unsigned long long*>(&h->done) = tag;
+}
+
+// Scalar recurrences and n-vector updates of one LSQR step, by one work-group,
+// once y = Abar^T u' / beta - beta v (first step: Abar^T u' / beta) is
+// complete in y[0, n): alpha = ||y||, v = y / alpha, the plane rotation, dy
+// and wd.  `s` is every thread's register copy of the state, updated here and
+// written back by thread 0 (no dependent loads of the state on this path).
+// With vout (LDS), the new v is also left there.  Returns false, with the
+// state marked failed, after a non-finite beta or alpha.
+__device__ bool lsqr_update(const LsqrArgs& a, LsqrState& s, const double* y, double beta,
+                            double alpha, bool first, double* vout) {
+  LsqrState* __restrict__ st = a.st;
+  const int n = a.n, t = threadIdx.x, nt = blockDim.x;
+  const double sighat = a.sighat;
+  double* v = a.vecs + n;
+  double* wd = a.vecs + 2 * n;
+  double* dy = a.vecs + 3 * n;
+  if (!isfinite(beta) || !isfinite(alpha)) {
+    s.status = SNS_ERR_NUMERICAL;
+    s.done = 1;
+    __syncthreads();
+    if (t == 0) {
+      st->status = s.status;
+      st->done = 1;
+    }
+    return false;
+  }
+  const double inva = alpha > 0.0 ? 1.0 / alpha : 0.0;
+  if (first) {
+    // beta_1 u_1 = r0, alpha_1 v_1 = Abar^T u_1, wd_1 = v_1, phibar = beta_1, rhobar = alpha_1
+    for (int j = t; j < n; j += nt) {
+      const double vj = y[j] * inva;
+      v[j] = vj;
+      wd[j] = vj;
+      dy[j] = 0.0;
+      if (vout) vout[j] = vj;
+    }
+    s.beta = beta;
+    s.alpha = alpha;
+    s.phibar = beta;
+    s.rhobar = alpha;
+    s.iter = 0;
+    s.gamma = beta > 0.0 ? alpha / beta : 0.0;
+    s.ratio = sighat > 0.0 ? alpha / sighat : alpha;
+    if (beta == 0.0 || alpha == 0.0 || s.max_iters <= 0) s.done = 1;
+  } else {
+    const double rhobar = s.rhobar, phibar = s.phibar;
+    const double rho = hypot(rhobar, beta);
+    const double c = rhobar / rho, sn = beta / rho;
+    const double theta = sn * alpha;
+    const double phi = c * phibar;
+    const double f1 = phi / rho, f2 = theta / rho;
+    for (int j = t; j < n; j += nt) {
+      const double vj = y[j] * inva;
+      const double wdj = wd[j];
+      dy[j] += f1 * wdj;
+      wd[j] = vj - f2 * wdj;
+      v[j] = vj;
+      if (vout) vout[j] = vj;
+    }
+    s.beta = beta;
+    s.alpha = alpha;
+    s.rhobar = -c * alpha;
+    s.phibar = sn * phibar;
+    s.iter += 1;
+    s.gamma = beta > 0.0 ? alpha / beta : 0.0;
+    const double ratio = alpha * fabs(c);
+    s.ratio = sighat > 0.0 ? ratio / sighat : ratio;
+    bool stop = beta == 0.0 || alpha == 0.0 || s.iter >= s.max_iters;
+    if (s.stop > 0.0 && ratio <= s.stop) stop = true;
+    if (stop) {
+      s.done = 1;
+      if (s.stop > 0.0 && ratio > s.stop && beta != 0.0 && alpha != 0.0)
+        s.status = SNS_ERR_NOT_CONVERGED;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    st->beta = s.beta;
+    st->alpha = s.alpha;
+    st->rhobar = s.rhobar;
+    st->phibar = s.phibar;
+    st->iter = s.iter;
+    st->gamma = s.gamma;
+    st->ratio = s.ratio;
+    st->done = s.done;
+    st->status = s.status;
+  }
+  return true;
+}
+
+// sum_j M[j * n + col] vec[j] over j in [j0, j1), one thread per column, in a
+// fixed order (four running sums); consecutive threads read consecutive
+// addresses.
+__device__ __forceinline__ double col_dot(const double* __restrict__ M, int n, int col, int j0,
+                                          int j1, const double* vec) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = j0;
+  for (; j + 16 <= j1; j += 16) {
+    double x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = M[(size_t)(j + k) * n + col];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc[k & 3] = fma(x[k], vec[j + k], acc[k & 3]);
+  }
+  for (int k = 0; j < j1; ++j, ++k) acc[k & 3] = fma(M[(size_t)j * n + col], vec[j], acc[k & 3]);
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+// The whole step of a problem with n <= kFuseMaxN, run by the last work-group
+// of k_lsqr_reduce to finish: z = A^T u' / beta from the reduction groups
+// (agent-scope loads: other work-groups wrote them in this launch),
+// y = X^T z - beta v (first step: X^T z; SAA-SAS after the residual pass:
+// z - beta v), the update, then w = X v for the next pass (SAA-SAS: w = v).
+// Each column's sums are split over kFuseParts threads (contiguous ranges of
+// j, combined in a fixed order); the triangular products also run over the
+// stored zeros of X up to the wave's column block, so every load is coalesced.
+__device__ void lsqr_fused_step(const LsqrArgs& a, double* zs, double* ys,
+                                double (*pp)[kFuseMaxN], double* red, PollSlot* ring) {
+  LsqrState* __restrict__ st = a.st;
+  LsqrState sc = *st;  // register copy, loaded once
+  const int n = a.n, t = threadIdx.x;
+  const int c = t % kFuseMaxN, q = t / kFuseMaxN;  // column, part
+  const int wlo = c & ~63, whi = wlo + 64 < n ? wlo + 64 : n;  // this wave's column block
+  double beta2 = 0.0;
+  for (int s = 0; s < kRedSplit; ++s)
+    beta2 += __hip_atomic_load(&a.nred2[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const double beta = sqrt(beta2);
+  const double invb = beta > 0.0 ? 1.0 / beta : 0.0;
+  const bool first = sc.iter < 0;
+  if (t < n) {
+    double z = 0.0;
+    for (int s = 0; s < kRedSplit; ++s)
+      z += __hip_atomic_load(&a.zred2[(size_t)s * n + t], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    zs[t] = z * invb;
+  }
+  __syncthreads();
+  const bool xtz = !(a.Y && !first);  // SAA-SAS after the residual pass: X^T is the identity
+  if (xtz && c < n) {
+    // X^T row c = X column c: Xr[j * n + c], nonzero for j <= c
+    const int j0 = q * whi / kFuseParts, j1 = (q + 1) * whi / kFuseParts;
+    pp[q][c] = col_dot(a.Xr, n, c, j0, j1, zs);
+  }
+  __syncthreads();
+  double y = 0.0;
+  if (t < n) {
+    y = zs[t];
+    if (xtz) {
+      y = pp[0][t];
+      for (int k = 1; k < kFuseParts; ++k) y += pp[k][t];
+    }
+    if (!first) y -= beta * a.vecs[n + t];
+    ys[t] = y;
+  }
+  const double alpha = sqrt(block_sum(y * y, red));
+  if (lsqr_update(a, sc, ys, beta, alpha, first, zs)) {
+    if (!a.Y && c < n) {
+      // X row c: Xc[j * n + c], nonzero for j >= c
+      const int len = n - wlo;
+      const int j0 = wlo + q * len / kFuseParts, j1 = wlo + (q + 1) * len / kFuseParts;
+      pp[q][c] = col_dot(a.Xc, n, c, j0, j1, zs);
+    }
+    __syncthreads();
+    if (t < n) {
+      double w = zs[t];
+      if (!a.Y) {
+        w = pp[0][t];
+        for (int k = 1; k < kFuseParts; ++k) w += pp[k][t];
+      }
+      a.vecs[t] = w;
+    }
+  }
+  if (t == 0) {
+    st->arrived = 0u;
+    if (ring) post_state(sc, st, ring);
+  }
+}
+
 // First level of the reduction of the G per-group partials: item (cx, s)
 // sums partials [s G / S, (s+1) G / S) for columns [64 cx, 64 cx + 64) into
-// zred2[s][.] (and, for cx = 0, the norms into nred2[s]).  Four thread groups
-// take every fourth partial, each with eight running sums (partials g,
-// g + 4, ..., g + 28 of a round of 32); all sums are combined in a fixed
-// order.
+// zred2[s][.] (and, for cx = 0, the norms into nred2[s]).  Sixteen thread
+// groups take every sixteenth partial, each with eight running sums (partials
+// g, g + 16, ..., g + 112 of a round of 128); all sums are combined in a fixed
+// order.  For n <= kFuseMaxN the results go to device-coherent memory
+// directly and the last item of the problem to finish runs the step.
 __device__ __forceinline__ void lsqr_reduce_item(const LsqrArgs& a, uint32_t loc,
-                                                 double (*part)[64], double* red) {
-  if (a.st->done) return;
+                                                 double (*part)[64], double* red, double* zs,
+                                                 double* ys, double (*pp)[kFuseMaxN], int* last,
+                                                 PollSlot* ring) {
+  const bool fused = a.n <= kFuseMaxN;
+  if (a.st->done) {
+    if (fused && ring && loc == 0 && threadIdx.x == 0) post_state(*a.st, a.st, ring);
+    return;
+  }
   const int n = a.n, G = a.grid;
   const uint32_t cxn = (uint32_t)((n + 63) / 64);
   const int cx = (int)(loc % cxn), s = (int)(loc / cxn);
@@ -244,34 +461,57 @@ __device__ __forceinline__ void lsqr_reduce_item(const LsqrArgs& a, uint32_t loc
   for (int k = 0; k < 8; ++k) acc[k] = 0.0;
   if (col < n) {
     int g = g0 + grp;
-    for (; g + 28 < g1; g += 32) {
+    for (; g + 7 * kRedGroups < g1; g += 8 * kRedGroups) {
       double v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) v[k] = zpart[(size_t)(g + 4 * k) * n + col];
+      for (int k = 0; k < 8; ++k) v[k] = zpart[(size_t)(g + kRedGroups * k) * n + col];
 #pragma unroll
       for (int k = 0; k < 8; ++k) acc[k] += v[k];
     }
-    for (int k = 0; g < g1; g += 4, ++k) acc[k] += zpart[(size_t)g * n + col];
+    for (int k = 0; g < g1; g += kRedGroups, ++k) acc[k] += zpart[(size_t)g * n + col];
   }
   part[grp][cl] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
-  if (t < 64 && col < n)
-    a.zred2[(size_t)s * n + col] = ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t];
+  if (t < 64 && col < n) {
+    double zr = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRedGroups; k += 4)
+      zr += (part[k][t] + part[k + 1][t]) + (part[k + 2][t] + part[k + 3][t]);
+    if (fused)
+      __hip_atomic_store(&a.zred2[(size_t)s * n + col], zr, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    else
+      a.zred2[(size_t)s * n + col] = zr;
+  }
   if (cx == 0) {
     double q = 0.0;
-    for (int g = g0 + t; g < g1; g += 256) q += a.npart[g];
+    for (int g = g0 + t; g < g1; g += kRedThreads) q += a.npart[g];
     q = block_sum(q, red);
-    if (t == 0) a.nred2[s] = q;
+    if (t == 0) {
+      if (fused) __hip_atomic_store(&a.nred2[s], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      else a.nred2[s] = q;
+    }
   }
+  if (!fused) return;
+  // every wave's stores complete before the item reports its arrival
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (t == 0) *last = atomicAdd(&a.st->arrived, 1u) == cxn * kRedSplit - 1u ? 1 : 0;
+  __syncthreads();
+  if (*last) lsqr_fused_step(a, zs, ys, pp, red, ring);
 }
 
-__global__ __launch_bounds__(256) void k_lsqr_reduce(const LsqrArgs* __restrict__ P, Map mp) {
-  __shared__ double part[4][64];
-  __shared__ double red[4];
+__global__ __launch_bounds__(kRedThreads) void k_lsqr_reduce(const LsqrArgs* __restrict__ P,
+                                                             Map mp, PollSlot* ring) {
+  __shared__ double part[kRedGroups][64];
+  __shared__ double red[kRedGroups];
+  __shared__ double zs[kFuseMaxN], ys[kFuseMaxN];
+  __shared__ double pp[kFuseParts][kFuseMaxN];
+  __shared__ int last;
   const uint32_t it = blockIdx.x;
   if (it >= mp.off[mp.nprob]) return;
   const int pi = map_find(mp, it);
-  lsqr_reduce_item(P[pi], it - mp.off[pi], part, red);
+  lsqr_reduce_item(P[pi], it - mp.off[pi], part, red, zs, ys, pp, &last, ring);
 }
 
 __global__ void k_lsqr_init(const LsqrArgs* __restrict__ P, Map mp) {
@@ -296,6 +536,7 @@ __global__ void k_lsqr_init(const LsqrArgs* __restrict__ P, Map mp) {
     st->done = a.max_iters <= 0 ? 1 : 0;
     st->status = SNS_OK;
     st->arrived = 0u;
+    st->steps = 0u;
   }
 }
 
@@ -343,17 +584,18 @@ __device__ __forceinline__ double wave_row_dot(const double* __restrict__ M, int
 // problem to finish (arrival counter) then runs the scalar recurrences and
 // the n-vector updates for the whole vector in a fixed order.
 __device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, double* sh,
-                                              bool* last) {
+                                              bool* last, PollSlot* ring) {
+  if (a.n <= kFuseMaxN) return;  // the step ran in k_lsqr_reduce
   LsqrState* __restrict__ st = a.st;
-  if (st->done) return;
+  if (st->done) {
+    if (ring && loc == 0 && threadIdx.x == 0) post_state(*st, st, ring);
+    return;
+  }
   const int n = a.n;
-  const double sighat = a.sighat;
   const uint32_t nitems = (uint32_t)((n + kGemvRows - 1) / kGemvRows);
   double* z = sh;        // n
   double* red = sh + n;  // 16 + kGemvRows
-  double* v = a.vecs + n;
-  double* wd = a.vecs + 2 * n;
-  double* dy = a.vecs + 3 * n;
+  const double* v = a.vecs + n;
   double* ybuf = a.vecs + 4 * n;
   const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wv = t >> 6;
   double beta2 = 0.0;
@@ -374,17 +616,20 @@ __device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, d
       // after the residual pass, SAA-SAS works on Y itself: X^T is the identity
       double yi = (a.Y && !first) ? z[i] : wave_row_dot(a.Xc, n, i, 0, i + 1, z);
       if (!first) yi -= beta * v[i];
-      if (lane == 0) {
-        ybuf[i] = yi;
-        red[16 + r] = yi * yi;
-      }
+      if (lane == 0) red[16 + r] = yi;
     } else if (lane == 0) {
       red[16 + r] = 0.0;
     }
   }
   __syncthreads();
   if (t == 0) {
-    for (int r = 0; r < kGemvRows; ++r) ysq += red[16 + r];
+    // thread 0 stores the item's rows of y, so its release fence covers them
+    for (int r = 0; r < kGemvRows; ++r) {
+      const double yi = red[16 + r];
+      const int i = (int)loc * kGemvRows + r;
+      if (i < n) ybuf[i] = yi;
+      ysq += yi * yi;
+    }
     a.ypart[loc] = ysq;
     __threadfence();
     const unsigned int prev = atomicAdd(&st->arrived, 1u);
@@ -396,87 +641,29 @@ __device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, d
   // ---- last item: scalars and n-vector updates ----
   double a2 = 0.0;
   for (uint32_t g = 0; g < nitems; ++g) a2 += a.ypart[g];  // same value on every thread
-  const double alpha = sqrt(a2);
-  if (!isfinite(beta) || !isfinite(alpha)) {
-    __syncthreads();
-    if (t == 0) {
-      st->status = SNS_ERR_NUMERICAL;
-      st->done = 1;
-      st->arrived = 0u;
-    }
-    return;
+  LsqrState sc = *st;
+  (void)lsqr_update(a, sc, ybuf, beta, sqrt(a2), first, nullptr);
+  if (t == 0) {
+    st->arrived = 0u;
+    if (ring) post_state(sc, st, ring);
   }
-  const double inva = alpha > 0.0 ? 1.0 / alpha : 0.0;
-  if (first) {
-    // beta_1 u_1 = r0, alpha_1 v_1 = Abar^T u_1, wd_1 = v_1, phibar = beta_1, rhobar = alpha_1
-    for (int j = t; j < n; j += nt) {
-      const double vj = ybuf[j] * inva;
-      v[j] = vj;
-      wd[j] = vj;
-      dy[j] = 0.0;
-    }
-    __syncthreads();
-    if (t == 0) {
-      st->beta = beta;
-      st->alpha = alpha;
-      st->phibar = beta;
-      st->rhobar = alpha;
-      st->iter = 0;
-      st->gamma = beta > 0.0 ? alpha / beta : 0.0;
-      st->ratio = sighat > 0.0 ? alpha / sighat : alpha;
-      if (beta == 0.0 || alpha == 0.0 || st->max_iters <= 0) st->done = 1;
-    }
-  } else {
-    const double rhobar = st->rhobar, phibar = st->phibar;
-    const double rho = hypot(rhobar, beta);
-    const double c = rhobar / rho, s = beta / rho;
-    const double theta = s * alpha;
-    const double phi = c * phibar;
-    const double f1 = phi / rho, f2 = theta / rho;
-    for (int j = t; j < n; j += nt) {
-      const double vj = ybuf[j] * inva;
-      const double wdj = wd[j];
-      dy[j] += f1 * wdj;
-      wd[j] = vj - f2 * wdj;
-      v[j] = vj;
-    }
-    __syncthreads();
-    if (t == 0) {
-      st->beta = beta;
-      st->alpha = alpha;
-      st->rhobar = -c * alpha;
-      st->phibar = s * phibar;
-      st->iter += 1;
-      st->gamma = beta > 0.0 ? alpha / beta : 0.0;
-      const double ratio = alpha * fabs(c);
-      st->ratio = sighat > 0.0 ? ratio / sighat : ratio;
-      bool stop = beta == 0.0 || alpha == 0.0 || st->iter >= st->max_iters;
-      if (st->stop > 0.0 && ratio <= st->stop) stop = true;
-      if (stop) {
-        st->done = 1;
-        if (st->stop > 0.0 && ratio > st->stop && beta != 0.0 && alpha != 0.0)
-          st->status = SNS_ERR_NOT_CONVERGED;
-      }
-    }
-  }
-  if (t == 0) st->arrived = 0u;
 }
 
 __global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(const LsqrArgs* __restrict__ P,
-                                                           Map mp) {
+                                                           Map mp, PollSlot* ring) {
   extern __shared__ double sh[];
   __shared__ bool last;
   const uint32_t it = blockIdx.x;
   if (it >= mp.off[mp.nprob]) return;
   const int pi = map_find(mp, it);
-  lsqr_xtz_item(P[pi], it - mp.off[pi], sh, &last);
+  lsqr_xtz_item(P[pi], it - mp.off[pi], sh, &last, ring);
 }
 
 // mode 0: w_pass = X v for the next pass (skipped once the problem stopped);
 // mode 1: x = x0 + X dy.  Row i of X = Xr[i * n + j], j >= i.
 __device__ __forceinline__ void lsqr_xv_item(const LsqrArgs& a, uint32_t loc, int mode,
                                              double* vec) {
-  if (mode == 0 && a.st->done) return;
+  if (mode == 0 && (a.st->done || a.n <= kFuseMaxN)) return;  // small n: done in k_lsqr_reduce
   const int n = a.n;
   const double* vin = mode == 0 ? a.vecs + n : a.vecs + 3 * n;
   double* out = mode == 0 ? a.vecs : a.x;
@@ -764,6 +951,7 @@ LsqrJob build_lsqr_job(ArgTable& t, const std::vector<LsqrProb>& p, bool f64) {
     red.push_back((uint32_t)(((n + 63) / 64) * kRedSplit));
     gemv.push_back((uint32_t)((n + kGemvRows - 1) / kGemvRows));
     j.maxn = n > j.maxn ? n : j.maxn;
+    if (n > kFuseMaxN) j.unfused = true;
   }
   j.all = t.add(all.data(), all.size());
   uint32_t tmp = 0;
@@ -808,17 +996,21 @@ sns_status launch_lsqr_setup(const LsqrJob& j, hipStream_t s) {
   return launch_form_y(j.saa, s);
 }
 
-sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t s) {
+sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t s, PollSlot* ring) {
   if (j.count == 0) return SNS_OK;
   for (const LsqrJob::Cls& c : j.cls) {
     if (j.f64) launch_pass_v<double, 2>(c, s);
     else launch_pass_v<float, 4>(c, s);
   }
-  SNS_LAUNCH("lsqr_reduce", k_lsqr_reduce, dim3(grid_for(j.nred)), dim3(256), 0, s, j.all, j.mred);
-  SNS_LAUNCH("lsqr_xtz", k_lsqr_xtz, dim3(grid_for(j.ngemv)), dim3(kGemvThreads),
-             ((size_t)j.maxn + 16 + kGemvRows) * sizeof(double), s, j.all, j.mgemv);
-  SNS_LAUNCH("lsqr_xv", k_lsqr_xv, dim3(grid_for(j.ngemv)), dim3(kGemvThreads),
-             (size_t)j.maxn * sizeof(double), s, j.all, j.mgemv, 0);
+  PollSlot* r = j.count == 1 ? ring : nullptr;
+  SNS_LAUNCH("lsqr_reduce", k_lsqr_reduce, dim3(grid_for(j.nred)), dim3(kRedThreads), 0, s, j.all,
+             j.mred, r);
+  if (j.unfused) {
+    SNS_LAUNCH("lsqr_xtz", k_lsqr_xtz, dim3(grid_for(j.ngemv)), dim3(kGemvThreads),
+               ((size_t)j.maxn + 16 + kGemvRows) * sizeof(double), s, j.all, j.mgemv, r);
+    SNS_LAUNCH("lsqr_xv", k_lsqr_xv, dim3(grid_for(j.ngemv)), dim3(kGemvThreads),
+               (size_t)j.maxn * sizeof(double), s, j.all, j.mgemv, 0);
+  }
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }
@@ -849,19 +1041,21 @@ sns_status launch_lsqr_flags(const LsqrJob& j, int* out, hipStream_t s) {
 
 namespace {
 
-// Host-side view of the device stop state, copied after every LSQR step into
-// pinned memory so the host can decide how far ahead to enqueue.
+// Host-side view of the device stop state: pinned slots that k_lsqr_xtz
+// writes after every iteration of a single problem, one event per slot.
 struct PollRing {
-  static constexpr int kSlots = 8;
-  LsqrState* slot = nullptr;  // pinned host memory
-  hipEvent_t ev[kSlots] = {};
+  PollSlot* slot = nullptr;  // pinned host memory
+  hipEvent_t ev[kPollSlots] = {};
   bool ok = false;
   PollRing() {
-    if (hipHostMalloc((void**)&slot, sizeof(LsqrState) * kSlots, hipHostMallocDefault) !=
+    if (hipHostMalloc((void**)&slot, sizeof(PollSlot) * kPollSlots, hipHostMallocDefault) !=
         hipSuccess)
       return;
-    for (int i = 0; i < kSlots; ++i)
+    for (int i = 0; i < kPollSlots; ++i) {
+      slot[i].done = 0;
+      slot[i].step = -1;
       if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) return;
+    }
     ok = true;
   }
 };
@@ -875,7 +1069,7 @@ PollRing& poll_ring() {
 
 // One problem: set-up, iterations, final update.  Iteration 0 is the
 // residual pass r0 = b - A x0 plus the start-up step.  With `adaptive`, the
-// host reads the device stop state back while at most two iterations are in
+// host reads the device stop state while at most two iterations are in
 // flight; otherwise all max_iters + 1 steps are enqueued and the ones after
 // the stop rule return at once.
 sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipStream_t s) {
@@ -895,10 +1089,16 @@ sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipSt
     // unread iteration, predict from the geometric decay of the stop ratio
     // whether that iteration converges; if so, wait for it instead, so that no
     // launch is issued after the stop rule has fired.
-    const int K = PollRing::kSlots;
-    auto post = [&](int it) {
-      SNS_HIP_TRY(hipMemcpyAsync(&ring.slot[it % K], st, sizeof(LsqrState), hipMemcpyDeviceToHost,
-                                 s));
+    const int K = kPollSlots;
+    // the {done, step} word of slot k (low half done, high half step)
+    auto tag = [&](int k) -> volatile unsigned long long& {
+      return *reinterpret_cast<volatile unsigned long long*>(&ring.slot[k].done);
+    };
+    // Iteration it: clear its slot's step tag, launch, mark with an event.
+    auto launch = [&](int it) {
+      tag(it % K) = 0xFFFFFFFF00000000ull;
+      sns_status r = launch_lsqr_iteration(j, s, ring.slot);
+      if (r != SNS_OK) return r;
       SNS_HIP_TRY(hipEventRecord(ring.ev[it % K], s));
       return SNS_OK;
     };
@@ -907,15 +1107,27 @@ sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipSt
     int known = -1;  // last iteration whose state has been read
     auto read = [&](int it) {
       SNS_HIP_TRY(hipEventSynchronize(ring.ev[it % K]));
-      const LsqrState& h = ring.slot[it % K];
-      done = h.done != 0;
+      // the slot normally carries the iteration's tag once its event is done;
+      // allow the posted write a moment, then read the device state instead
+      unsigned long long w = tag(it % K);
+      for (int spin = 0; (int)(w >> 32) != it && spin < 100000; ++spin) w = tag(it % K);
+      double ratio;
+      if ((int)(w >> 32) == it) {
+        done = (unsigned int)w != 0u;
+        ratio = *reinterpret_cast<volatile double*>(&ring.slot[it % K].ratio);
+      } else {
+        LsqrState d;
+        SNS_HIP_TRY(hipStreamSynchronize(s));
+        SNS_HIP_TRY(hipMemcpy(&d, st, sizeof(d), hipMemcpyDeviceToHost));
+        done = d.done != 0;
+        ratio = d.ratio;
+      }
       r_prev = r_last;
-      r_last = h.ratio * (sighat > 0.0 ? sighat : 1.0);
+      r_last = ratio * (sighat > 0.0 ? sighat : 1.0);
       known = it;
       return SNS_OK;
     };
-    if ((e = launch_lsqr_iteration(j, s)) != SNS_OK) return e;
-    if ((e = post(0)) != SNS_OK) return e;
+    if ((e = launch(0)) != SNS_OK) return e;
     int next = 1;
     while (next <= max_iters) {
       if (known < next - 1) {
@@ -933,8 +1145,7 @@ sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipSt
         }
       }
       if (known == next - 1 && done) break;
-      if ((e = launch_lsqr_iteration(j, s)) != SNS_OK) return e;
-      if ((e = post(next)) != SNS_OK) return e;
+      if ((e = launch(next)) != SNS_OK) return e;
       ++next;
       if (known < next - 2) {
         if ((e = read(next - 2)) != SNS_OK) return e;
