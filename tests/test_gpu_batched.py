@@ -125,3 +125,27 @@ def test_batch_rejects_mixed_dtypes(gpu_lib):
     with pytest.raises(sns.SnsError):
         sns.lstsq_batched([_dev(a.A, torch), _dev(b.A, torch)], [_dev(a.b, torch), _dev(b.b, torch)],
                           [64, 64], [1, 2])
+
+
+def test_batch_straddles_fused_step_limit(gpu_lib):
+    """Problems with n <= 256 run the LSQR step inside the reduction kernel,
+    larger ones in the separate step kernels; one batch holding both kinds
+    matches the solo calls bit for bit, and FP64 results with a fixed
+    iteration count agree with the oracle's SAP-SAS on both sides of the
+    limit."""
+    import torch
+    sns = gpu_lib
+    mix = [(6000, 256), (6500, 258), (5000, 254), (7000, 300), (4000, 16)]  # rows of 16 bytes
+    probs = _problems(torch, dt=np.float64, mix=mix, seed0=1300)
+    got = _batch(sns, probs, True, 6, 0.0, True)
+    _same(got, _solo(sns, probs, True, 6, 0.0))
+    for (p, A, b, d, seed), (x, info) in zip(probs, got):
+        r = OSV.sap_sas(p.A, p.b, "count", seed, d, 6, rtol=0.0)
+        assert info.iters == 6
+        assert np.linalg.norm(x - r.x) <= 1e-9 * np.linalg.norm(r.x)
+    probs32 = _problems(torch, mix=[(40000, 256), (40000, 260), (20000, 64)], seed0=1400)
+    solo = _solo(sns, probs32, True, 80, 1e-6)
+    _same(_batch(sns, probs32, True, 80, 1e-6, True), solo)
+    for (p, *_), (x, info) in zip(probs32, solo):
+        assert info.status == 0
+        assert OM.metrics(p.A, p.b, x, OM.lstsq_exact(p.A, p.b))["RE"] <= 1e-6
