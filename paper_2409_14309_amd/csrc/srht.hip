@@ -12,7 +12,8 @@
 // so the transform is a sequence of butterfly stages, one per bit, in any
 // order.  Full passes (k_srht_pass) each apply the stages of up to 8
 // consecutive bits [lo, lo + nb): a work-group loads the 2^nb rows that differ
-// only in those bits (row segments of 32 columns: 128 bytes fp32, 256 fp64),
+// only in those bits (row segments of 32 columns: 128 bytes fp32, two columns
+// per lane; 256 bytes fp64),
 // applies the stages in registers and one LDS exchange, and writes the result
 // back in place of the same rows (pass 1 reads D [A | b], zero-padded; later
 // passes ping-pong between two m' x C buffers, C = n + 1 with b, rows padded
@@ -45,76 +46,130 @@ __device__ __forceinline__ uint32_t had_word(uint64_t seed, uint64_t idx, uint32
   }
 }
 
+// VW consecutive columns of one row, moved with one load or store (8 bytes for
+// two fp32 values).
+template <typename T, int VW>
+struct Pk {
+  T e[VW];
+};
+
+template <typename T, int VW>
+__device__ __forceinline__ Pk<T, VW> pk_load(const T* p) {
+  Pk<T, VW> r;
+  if constexpr (VW == 1) {
+    r.e[0] = *p;
+  } else {
+    typedef T VT __attribute__((ext_vector_type(VW)));
+    const VT v = *reinterpret_cast<const VT*>(p);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) r.e[e] = v[e];
+  }
+  return r;
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void pk_store(T* p, const Pk<T, VW>& x) {
+  if constexpr (VW == 1) {
+    *p = x.e[0];
+  } else {
+    typedef T VT __attribute__((ext_vector_type(VW)));
+    VT v;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) v[e] = x.e[e];
+    *reinterpret_cast<VT*>(p) = v;
+  }
+}
+
+template <typename T, int VW>
+__device__ __forceinline__ void pk_butterfly(Pk<T, VW>& a, Pk<T, VW>& b) {
+#pragma unroll
+  for (int e = 0; e < VW; ++e) {
+    const T x = a.e[e], y = b.e[e];
+    a.e[e] = x + y;
+    b.e[e] = x - y;
+  }
+}
+
 // One full pass over the bits [lo, lo + NB): work-group (o, ct) transforms
 // the 2^NB rows row(j) = (o mod 2^lo) + (j << lo) + ((o >> lo) << (lo + NB))
-// over columns [CW ct, CW ct + CW).  Thread (g, c), g < RT, holds j = g + RT k
-// and applies the stages of the bits of k in registers; one LDS exchange
-// (row stride CW + 1) then gives each thread groups of RT consecutive j for
-// the stages of the bits of g.  src == nullptr: the first pass, reading
-// D [A | b] (rows past m are zero).
-template <typename T, int CW, int NB>
+// over columns [CW VW ct, CW VW (ct + 1)), VW columns per thread.  Thread
+// (g, c), g < RT, holds j = g + RT k and applies the stages of the bits of k
+// in registers; one LDS exchange (row stride CW + 1 packs) then gives each
+// thread groups of RT consecutive j for the stages of the bits of g.
+// src == nullptr: the first pass, reading D [A | b] (rows past m are zero);
+// `avec`: A's rows allow VW-wide loads (base and row stride aligned).
+template <typename T, int VW, int CW, int NB>
 __global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ src,
                                                          const T* __restrict__ A, int64_t ld,
                                                          int64_t m, int n, const T* __restrict__ b,
                                                          uint64_t seed, int lo, int ctiles,
-                                                         T* __restrict__ dst, int C,
-                                                         int ldb) {
+                                                         T* __restrict__ dst, int C, int ldb,
+                                                         bool avec) {
+  typedef Pk<T, VW> P;
   constexpr int BR = 1 << NB;
   constexpr int RT0 = kHThreads / CW;
   constexpr int RT = RT0 < BR ? RT0 : BR, NV = BR / RT, LDT = CW + 1;
-  __shared__ T tile[BR * LDT];
+  __shared__ P tile[BR * LDT];
   __shared__ unsigned char neg[BR];  // first pass: sign bits of the block's rows
   const int t = threadIdx.x, g = t / CW, c = t % CW;
   const int ct = (int)(blockIdx.x % (unsigned)ctiles);
   const int64_t o = blockIdx.x / (unsigned)ctiles;
   const int64_t olow = o & ((int64_t(1) << lo) - 1), ohigh = o >> lo;
   auto row = [&](int j) -> int64_t { return olow + ((int64_t)j << lo) + (ohigh << (lo + NB)); };
-  const int col = ct * CW + c;
+  const int col = (ct * CW + c) * VW;  // first column of this thread's pack
   const bool active = g < RT;
   if (!src) {  // lo = 0: the block's rows are consecutive, one Philox call per 4 rows
     for (int j = t; j < BR; j += kHThreads) neg[j] = (unsigned char)(had_word(seed, (uint64_t)row(j), 2u) >> 31);
     __syncthreads();
   }
   // Loads: the common cases have no branch inside the loop, so every load of
-  // the block is in flight before the first use.
-  T v[NV];
+  // the block is in flight before the first use.  Columns past C (inside the
+  // padded row of the work buffers) carry zeros or values nobody reads.
+  P v[NV];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = T(0);
+  for (int k = 0; k < NV; ++k)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) v[k].e[e] = T(0);
   if (active) {
     if (src) {
       if (col < C) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = src[row(g + RT * k) * ldb + col];
+        for (int k = 0; k < NV; ++k) v[k] = pk_load<T, VW>(src + row(g + RT * k) * ldb + col);
       }
     } else {
       const bool full = row(BR - 1) < m;  // the first pass reads consecutive rows
-      if (full && col < n) {
+      if (full && col + VW <= n && (VW == 1 || avec)) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = A[row(g + RT * k) * ld + col];
+        for (int k = 0; k < NV; ++k) v[k] = pk_load<T, VW>(A + row(g + RT * k) * ld + col);
       } else if (col <= n) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
           const int64_t i = row(g + RT * k);
-          if (i < m) v[k] = col < n ? A[i * ld + col] : (b ? b[i] : T(0));
+          if (i < m) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+              const int cc = col + e;
+              v[k].e[e] = cc < n ? A[i * ld + cc] : (cc == n && b ? b[i] : T(0));
+            }
+          }
         }
       }
 #pragma unroll
-      for (int k = 0; k < NV; ++k) v[k] = neg[g + RT * k] ? -v[k] : v[k];
+      for (int k = 0; k < NV; ++k)
+        if (neg[g + RT * k])
+#pragma unroll
+          for (int e = 0; e < VW; ++e) v[k].e[e] = -v[k].e[e];
     }
   }
 #pragma unroll
   for (int h = 1; h < NV; h <<= 1)
 #pragma unroll
     for (int k = 0; k < NV; ++k)
-      if ((k & h) == 0) {
-        const T x = v[k], y = v[k + h];
-        v[k] = x + y;
-        v[k + h] = x - y;
-      }
+      if ((k & h) == 0) pk_butterfly<T, VW>(v[k], v[k + h]);
   if constexpr (RT == 1) {
     if (active && col < C) {
 #pragma unroll
-      for (int k = 0; k < NV; ++k) dst[row(k) * ldb + col] = v[k];
+      for (int k = 0; k < NV; ++k) pk_store<T, VW>(dst + row(k) * ldb + col, v[k]);
     }
   } else {
     if (active) {
@@ -123,22 +178,18 @@ __global__ __launch_bounds__(kHThreads) void k_srht_pass(const T* __restrict__ s
     }
     __syncthreads();
     for (int q = t; q < NV * CW; q += kHThreads) {
-      const int grp = q / CW, cc = q % CW, ccol = ct * CW + cc;
-      T w[RT];
+      const int grp = q / CW, cc = q % CW, ccol = (ct * CW + cc) * VW;
+      P w[RT];
 #pragma unroll
       for (int r = 0; r < RT; ++r) w[r] = tile[(grp * RT + r) * LDT + cc];
 #pragma unroll
       for (int h = 1; h < RT; h <<= 1)
 #pragma unroll
         for (int r = 0; r < RT; ++r)
-          if ((r & h) == 0) {
-            const T x = w[r], y = w[r + h];
-            w[r] = x + y;
-            w[r + h] = x - y;
-          }
+          if ((r & h) == 0) pk_butterfly<T, VW>(w[r], w[r + h]);
       if (ccol < C) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) dst[row(grp * RT + r) * ldb + ccol] = w[r];
+        for (int r = 0; r < RT; ++r) pk_store<T, VW>(dst + row(grp * RT + r) * ldb + ccol, w[r]);
       }
     }
   }
@@ -200,21 +251,25 @@ HadPlan had_plan(const sns_matrix& A, bool with_b) {
   return p;
 }
 
-template <typename T, int CW, int NB>
+template <typename T, int VW, int CW, int NB>
 void launch_pass(dim3 grid, hipStream_t st, const T* src, const sns_matrix& A, const void* b,
-                 uint64_t seed, int lo, int ctiles, T* dst, int C, int ldb) {
-  SNS_LAUNCH(src ? "srht_pass" : "srht_pass1", (k_srht_pass<T, CW, NB>), grid, dim3(kHThreads), 0, st, src,
-             static_cast<const T*>(A.values), A.ld, A.m, (int)A.n, static_cast<const T*>(b), seed,
-             lo, ctiles, dst, C, ldb);
+                 uint64_t seed, int lo, int ctiles, T* dst, int C, int ldb, bool avec) {
+  SNS_LAUNCH(src ? "srht_pass" : "srht_pass1", (k_srht_pass<T, VW, CW, NB>), grid,
+             dim3(kHThreads), 0, st, src, static_cast<const T*>(A.values), A.ld, A.m, (int)A.n,
+             static_cast<const T*>(b), seed, lo, ctiles, dst, C, ldb, avec);
 }
 
-template <typename T, int CW>
+// VW columns per thread, CW packs per work-group (a row segment of CW VW
+// values: 128 bytes for fp32, 256 for fp64).
+template <typename T, int VW, int CW>
 sns_status launch_had(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b, void* SA,
                       void* Sb, void* ws, hipStream_t st) {
   const HadPlan p = had_plan(A, b != nullptr);
   const size_t buf = align_up((size_t)p.mp * p.ldb * sizeof(T));
   T* Bs[2] = {static_cast<T*>(ws), reinterpret_cast<T*>(static_cast<char*>(ws) + buf)};
-  const int ctiles = (p.C + CW - 1) / CW;
+  static_assert(32 % (CW * VW) == 0 || (CW * VW) % 32 == 0, "tiles inside the padded rows");
+  const int ctiles = (p.C + CW * VW - 1) / (CW * VW);
+  const bool avec = reinterpret_cast<uintptr_t>(A.values) % (VW * sizeof(T)) == 0 && A.ld % VW == 0;
   const T* src = nullptr;
   int lo = 0;
   for (int q = 0; q < p.P; ++q) {
@@ -223,17 +278,20 @@ sns_status launch_had(const sns_matrix& A, uint32_t d, uint64_t seed, const void
     const uint64_t blocks = (p.mp >> nb) * (uint64_t)ctiles;
     if (blocks > 0x7FFFFFFFull) return SNS_ERR_SHAPE;
     const dim3 grid((unsigned)blocks);
+#define SNS_PASS(NBV) \
+  launch_pass<T, VW, CW, NBV>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb, avec)
     switch (nb) {
-      case 0: launch_pass<T, CW, 0>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      case 1: launch_pass<T, CW, 1>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      case 2: launch_pass<T, CW, 2>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      case 3: launch_pass<T, CW, 3>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      case 4: launch_pass<T, CW, 4>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      case 5: launch_pass<T, CW, 5>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      case 6: launch_pass<T, CW, 6>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      case 7: launch_pass<T, CW, 7>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
-      default: launch_pass<T, CW, 8>(grid, st, src, A, b, seed, lo, ctiles, dst, p.C, p.ldb); break;
+      case 0: SNS_PASS(0); break;
+      case 1: SNS_PASS(1); break;
+      case 2: SNS_PASS(2); break;
+      case 3: SNS_PASS(3); break;
+      case 4: SNS_PASS(4); break;
+      case 5: SNS_PASS(5); break;
+      case 6: SNS_PASS(6); break;
+      case 7: SNS_PASS(7); break;
+      default: SNS_PASS(8); break;
     }
+#undef SNS_PASS
     src = dst;
     lo += nb;
   }
@@ -256,8 +314,8 @@ size_t hadamard_workspace_bytes(const sns_matrix& A, uint32_t /*d*/) {
 sns_status launch_hadamard_sketch(const sns_matrix& A, uint32_t d, uint64_t seed, const void* b,
                                   void* SA, void* Sb, void* ws, hipStream_t st) {
   if (A.layout != SNS_DENSE_ROWMAJOR) return SNS_ERR_DTYPE;
-  if (A.dtype == SNS_F64) return launch_had<double, 32>(A, d, seed, b, SA, Sb, ws, st);
-  return launch_had<float, 32>(A, d, seed, b, SA, Sb, ws, st);
+  if (A.dtype == SNS_F64) return launch_had<double, 1, 32>(A, d, seed, b, SA, Sb, ws, st);
+  return launch_had<float, 2, 32>(A, d, seed, b, SA, Sb, ws, st);
 }
 
 }  // namespace sns
