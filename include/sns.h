@@ -339,8 +339,11 @@ sns_status sns_tune_save(const char* path);
  * bytes, truncated and NUL-terminated), returning the untruncated length.
  * SNS_TRACE=1 in the environment enables timing at the first call and prints
  * the summary to stderr at exit.  Not for use while another thread launches
- * library work. */
+ * library work.  sns_timing_select restricts timing to the kernels named in
+ * `names` (host string, comma-separated, copied; NULL or "" selects every
+ * kernel): each timed launch adds two event records to its stream. */
 void sns_timing_enable(int on);
+void sns_timing_select(const char* names);
 void sns_timing_reset(void);
 int sns_timing_summary(char* buf, size_t len);
 

@@ -113,6 +113,7 @@ _SIGS = {
     "sns_tune_load": (C.c_int, [C.c_char_p]),
     "sns_tune_save": (C.c_int, [C.c_char_p]),
     "sns_timing_enable": (None, [C.c_int]),
+    "sns_timing_select": (None, [C.c_char_p]),
     "sns_timing_reset": (None, []),
     "sns_timing_summary": (C.c_int, [C.c_char_p, C.c_size_t]),
 }
@@ -372,6 +373,11 @@ def sns_tune_save(path: str):
 
 def sns_timing_enable(on: bool = True):
     load().sns_timing_enable(1 if on else 0)
+
+
+def sns_timing_select(names=None):
+    """Time only the named kernels (an iterable of names, or None for all)."""
+    load().sns_timing_select(None if names is None else ",".join(names).encode())
 
 
 def sns_timing_reset():

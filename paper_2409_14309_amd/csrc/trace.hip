@@ -1,8 +1,11 @@
-// Per-kernel timing: when enabled, every launch of the library is bracketed by
-// two HIP events recorded on the launch stream.  Durations are read back on
-// demand (sns_timing_summary) and summed per kernel name.  Enabled by
+// Per-kernel timing: when enabled, every launch of the library (or of the
+// kernels named by sns_timing_select) is bracketed by two HIP events recorded
+// on the launch stream.  Durations are read back on demand
+// (sns_timing_summary) and summed per kernel name.  Enabled by
 // sns_timing_enable(1) or by the environment variable SNS_TRACE=1, which also
-// prints the summary to stderr when the process exits.
+// prints the summary to stderr when the process exits.  Each bracketed launch
+// costs a few microseconds of device time for the two event records, so a
+// caller timing a whole solve selects only the kernels it reports.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -31,6 +34,7 @@ struct Registry {
   std::vector<hipEvent_t> pool;  // free events
   std::vector<Rec> recs;
   std::map<std::string, std::pair<double, long long>> done;  // name -> (ms, launches)
+  std::vector<std::string> only;  // kernels to time; empty: all
 };
 
 Registry& reg() {
@@ -98,6 +102,11 @@ void timing_begin(const char* name, hipStream_t s) {
   std::lock_guard<std::mutex> g(r.mu);
   check_env(r);
   if (!r.on) return;
+  if (!r.only.empty()) {
+    bool hit = false;
+    for (const std::string& k : r.only) hit = hit || k == name;
+    if (!hit) return;
+  }
   // launches being captured into a graph are not timed
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
@@ -128,6 +137,23 @@ void sns_timing_enable(int on) {
   std::lock_guard<std::mutex> g(r.mu);
   sns::check_env(r);
   r.on = on != 0;
+}
+
+void sns_timing_select(const char* names) {
+  sns::Registry& r = sns::reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  r.only.clear();
+  if (!names) return;
+  std::string cur;
+  for (const char* c = names;; ++c) {
+    if (*c == ',' || *c == '\0') {
+      if (!cur.empty()) r.only.push_back(cur);
+      cur.clear();
+      if (*c == '\0') break;
+    } else {
+      cur += *c;
+    }
+  }
 }
 
 void sns_timing_reset(void) {

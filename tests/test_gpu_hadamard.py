@@ -98,3 +98,23 @@ def test_hadamard_solve_reaches_target(gpu_lib):
     assert info.status == 0
     xs = OM.lstsq_exact(p.A, p.b)
     assert OM.metrics(p.A, p.b, x.cpu().numpy(), xs)["RE"] <= 1e-6
+
+
+@pytest.mark.parametrize("off,extra", [(1, 3), (0, 1), (2, 4)])
+def test_strided_views_of_A(gpu_lib, off, extra):
+    """A given as a column window of a wider array (row stride n + extra,
+    first column at offset off): odd strides and offsets take the
+    elementwise reads of the first pass, even ones the paired reads."""
+    import torch
+    m, n, d = 5000, 37, 256  # d a power of four: integer inputs give exact results
+    rng = np.random.default_rng(off * 10 + extra)
+    big = rng.integers(-8, 9, size=(m, n + extra)).astype(np.float32)
+    A = big[:, off:off + n]
+    b = rng.integers(-8, 9, size=m).astype(np.float32)
+    Adev = _dev(big, torch)[:, off:off + n]
+    assert Adev.stride(0) == n + extra
+    SA, Sb = gpu_lib.sketch(Adev, _dev(b, torch), "hadamard", d, 5)
+    torch.cuda.synchronize()
+    SAr, Sbr = OS.hadamard_apply(np.ascontiguousarray(A), b, 5, d)
+    assert np.array_equal(SA.cpu().numpy().astype(np.float64), SAr)
+    assert np.array_equal(Sb.cpu().numpy().astype(np.float64), Sbr)

@@ -38,7 +38,7 @@ def _qr_gpu(sns, torch, SA, Sb):
 
 @pytest.mark.parametrize("d,n", [(200, 50), (1024, 256), (600, 600), (2100, 130), (80, 1),
                                  (513, 17), (4000, 97), (512, 16), (1025, 300), (4097, 40),
-                                 (8192, 70), (257, 19)])
+                                 (8192, 70), (257, 19), (4000, 1000), (8192, 600)])
 def test_qr_solve_matches_oracle(gpu_lib, d, n):
     import torch
     rng = np.random.default_rng(d * 7 + n)
