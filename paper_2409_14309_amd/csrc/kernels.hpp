@@ -363,9 +363,11 @@ LsqrJob build_lsqr_job(ArgTable& t, const std::vector<LsqrProb>& p, bool f64);
 // finished problems skipping), the final update and the report.
 sns_status launch_lsqr_setup(const LsqrJob& j, hipStream_t st);
 // ring: pinned host slots (kPollSlots of them) that a single-problem job
-// posts its stop state to after every iteration; null for none.
+// posts its stop state to after every iteration, tagged with `epoch`; null
+// for none.
 struct PollSlot;
-sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t st, PollSlot* ring = nullptr);
+sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t st, PollSlot* ring = nullptr,
+                                 unsigned int epoch = 0);
 sns_status launch_lsqr_finish(const LsqrJob& j, hipStream_t st);
 sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipStream_t st);
 // Number of problems of the job that have not stopped, written to *out

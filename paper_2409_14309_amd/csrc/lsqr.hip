@@ -54,8 +54,17 @@ constexpr int kPollSlots = 8;
 struct PollSlot {
   double ratio;
   int done;  // done and step form one 64-bit word, written at once
-  int step;  // iteration the slot describes
+  int step;  // solve epoch (high 16 bits) and iteration (low 16 bits) the slot describes
 };
+// The ring of one solve: its slots and the epoch that tags its posts, so
+// that a post still in flight from an earlier solve never reads as current.
+struct PollRef {
+  PollSlot* slot;
+  unsigned int epoch;
+};
+__host__ __device__ inline int poll_tag(unsigned int epoch, unsigned int step) {
+  return (int)(((epoch & 0x7FFFu) << 16) | (step & 0xFFFFu));
+}
 
 namespace {
 
@@ -246,13 +255,14 @@ __global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(const LsqrArgs* _
 // travel in one 64-bit store, so the host never pairs a fresh tag with a stale
 // flag; the ratio only steers how far the host runs ahead.
 // `s` is the state as it now stands (a register copy or *st itself).
-__device__ __forceinline__ void post_state(const LsqrState& s, LsqrState* st, PollSlot* ring) {
+__device__ __forceinline__ void post_state(const LsqrState& s, LsqrState* st, PollRef ring) {
   const unsigned int k = s.steps;
   st->steps = k + 1u;
-  PollSlot* h = ring + k % kPollSlots;
+  PollSlot* h = ring.slot + k % kPollSlots;
   h->ratio = s.ratio;
   const unsigned long long tag =
-      ((unsigned long long)k << 32) | (unsigned long long)(unsigned int)s.done;
+      ((unsigned long long)(unsigned int)poll_tag(ring.epoch, k) << 32) |
+      (unsigned long long)(unsigned int)s.done;
   *reinterpret_cast<unsigned long long*>(&h->done) = tag;
 }
 
@@ -372,7 +382,7 @@ __device__ __forceinline__ double col_dot(const double* __restrict__ M, int n, i
 // j, combined in a fixed order); the triangular products also run over the
 // stored zeros of X up to the wave's column block, so every load is coalesced.
 __device__ void lsqr_fused_step(const LsqrArgs& a, double* zs, double* ys,
-                                double (*pp)[kFuseMaxN], double* red, PollSlot* ring) {
+                                double (*pp)[kFuseMaxN], double* red, PollRef ring) {
   LsqrState* __restrict__ st = a.st;
   LsqrState sc = *st;  // register copy, loaded once
   const int n = a.n, t = threadIdx.x;
@@ -429,7 +439,7 @@ __device__ void lsqr_fused_step(const LsqrArgs& a, double* zs, double* ys,
   }
   if (t == 0) {
     st->arrived = 0u;
-    if (ring) post_state(sc, st, ring);
+    if (ring.slot) post_state(sc, st, ring);
   }
 }
 
@@ -443,10 +453,10 @@ __device__ void lsqr_fused_step(const LsqrArgs& a, double* zs, double* ys,
 __device__ __forceinline__ void lsqr_reduce_item(const LsqrArgs& a, uint32_t loc,
                                                  double (*part)[64], double* red, double* zs,
                                                  double* ys, double (*pp)[kFuseMaxN], int* last,
-                                                 PollSlot* ring) {
+                                                 PollRef ring) {
   const bool fused = a.n <= kFuseMaxN;
   if (a.st->done) {
-    if (fused && ring && loc == 0 && threadIdx.x == 0) post_state(*a.st, a.st, ring);
+    if (fused && ring.slot && loc == 0 && threadIdx.x == 0) post_state(*a.st, a.st, ring);
     return;
   }
   const int n = a.n, G = a.grid;
@@ -502,7 +512,7 @@ __device__ __forceinline__ void lsqr_reduce_item(const LsqrArgs& a, uint32_t loc
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_lsqr_reduce(const LsqrArgs* __restrict__ P,
-                                                             Map mp, PollSlot* ring) {
+                                                             Map mp, PollRef ring) {
   __shared__ double part[kRedGroups][64];
   __shared__ double red[kRedGroups];
   __shared__ double zs[kFuseMaxN], ys[kFuseMaxN];
@@ -584,11 +594,11 @@ __device__ __forceinline__ double wave_row_dot(const double* __restrict__ M, int
 // problem to finish (arrival counter) then runs the scalar recurrences and
 // the n-vector updates for the whole vector in a fixed order.
 __device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, double* sh,
-                                              bool* last, PollSlot* ring) {
+                                              bool* last, PollRef ring) {
   if (a.n <= kFuseMaxN) return;  // the step ran in k_lsqr_reduce
   LsqrState* __restrict__ st = a.st;
   if (st->done) {
-    if (ring && loc == 0 && threadIdx.x == 0) post_state(*st, st, ring);
+    if (ring.slot && loc == 0 && threadIdx.x == 0) post_state(*st, st, ring);
     return;
   }
   const int n = a.n;
@@ -645,12 +655,12 @@ __device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, d
   (void)lsqr_update(a, sc, ybuf, beta, sqrt(a2), first, nullptr);
   if (t == 0) {
     st->arrived = 0u;
-    if (ring) post_state(sc, st, ring);
+    if (ring.slot) post_state(sc, st, ring);
   }
 }
 
 __global__ __launch_bounds__(kGemvThreads) void k_lsqr_xtz(const LsqrArgs* __restrict__ P,
-                                                           Map mp, PollSlot* ring) {
+                                                           Map mp, PollRef ring) {
   extern __shared__ double sh[];
   __shared__ bool last;
   const uint32_t it = blockIdx.x;
@@ -996,13 +1006,14 @@ sns_status launch_lsqr_setup(const LsqrJob& j, hipStream_t s) {
   return launch_form_y(j.saa, s);
 }
 
-sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t s, PollSlot* ring) {
+sns_status launch_lsqr_iteration(const LsqrJob& j, hipStream_t s, PollSlot* ring,
+                                  unsigned int epoch) {
   if (j.count == 0) return SNS_OK;
   for (const LsqrJob::Cls& c : j.cls) {
     if (j.f64) launch_pass_v<double, 2>(c, s);
     else launch_pass_v<float, 4>(c, s);
   }
-  PollSlot* r = j.count == 1 ? ring : nullptr;
+  const PollRef r{j.count == 1 ? ring : nullptr, epoch};
   SNS_LAUNCH("lsqr_reduce", k_lsqr_reduce, dim3(grid_for(j.nred)), dim3(kRedThreads), 0, s, j.all,
              j.mred, r);
   if (j.unfused) {
@@ -1046,6 +1057,7 @@ namespace {
 struct PollRing {
   PollSlot* slot = nullptr;  // pinned host memory
   hipEvent_t ev[kPollSlots] = {};
+  unsigned int epoch = 0;  // solves that used the ring on this thread
   bool ok = false;
   PollRing() {
     if (hipHostMalloc((void**)&slot, sizeof(PollSlot) * kPollSlots, hipHostMallocDefault) !=
@@ -1090,6 +1102,7 @@ sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipSt
     // whether that iteration converges; if so, wait for it instead, so that no
     // launch is issued after the stop rule has fired.
     const int K = kPollSlots;
+    const unsigned int epoch = ++ring.epoch;
     // the {done, step} word of slot k (low half done, high half step)
     auto tag = [&](int k) -> volatile unsigned long long& {
       return *reinterpret_cast<volatile unsigned long long*>(&ring.slot[k].done);
@@ -1097,7 +1110,7 @@ sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipSt
     // Iteration it: clear its slot's step tag, launch, mark with an event.
     auto launch = [&](int it) {
       tag(it % K) = 0xFFFFFFFF00000000ull;
-      sns_status r = launch_lsqr_iteration(j, s, ring.slot);
+      sns_status r = launch_lsqr_iteration(j, s, ring.slot, epoch);
       if (r != SNS_OK) return r;
       SNS_HIP_TRY(hipEventRecord(ring.ev[it % K], s));
       return SNS_OK;
@@ -1109,10 +1122,11 @@ sns_status run_lsqr_single(const LsqrJob& j, int max_iters, bool adaptive, hipSt
       SNS_HIP_TRY(hipEventSynchronize(ring.ev[it % K]));
       // the slot normally carries the iteration's tag once its event is done;
       // allow the posted write a moment, then read the device state instead
+      const int want = poll_tag(epoch, (unsigned int)it);
       unsigned long long w = tag(it % K);
-      for (int spin = 0; (int)(w >> 32) != it && spin < 100000; ++spin) w = tag(it % K);
+      for (int spin = 0; (int)(w >> 32) != want && spin < 100000; ++spin) w = tag(it % K);
       double ratio;
-      if ((int)(w >> 32) == it) {
+      if ((int)(w >> 32) == want) {
         done = (unsigned int)w != 0u;
         ratio = *reinterpret_cast<volatile double*>(&ring.slot[it % K].ratio);
       } else {
