@@ -143,3 +143,35 @@ def test_exact_recovery(gpu_lib):
     b = p.A @ p.x_true
     x, info = sns.lstsq(_dev(p.A, torch), _dev(b, torch), "count", 120, 9)
     assert np.linalg.norm(x.cpu().numpy() - p.x_true) <= 1e-11 * np.linalg.norm(p.x_true)
+
+
+def test_concurrent_solves_on_two_streams_from_one_thread(gpu_lib):
+    """Two refined solves issued back to back on two streams from one host
+    thread: the first returns with iterations possibly still in flight while
+    the second polls the same ring of pinned host slots.  Each must give the
+    answer of the same solve run alone."""
+    import torch
+    sns = gpu_lib
+    probs = [dense_ill_conditioned(200000, 64, seed=61, cond=1e6),
+             dense_ill_conditioned(150000, 48, seed=62, cond=1e6)]
+    devs = [(_dev(p.A, torch), _dev(p.b, torch)) for p in probs]
+    solo = [sns.lstsq(A, b, "count", 4 * A.shape[1], 7, refine=True, max_iters=100, rtol=1e-6)
+            for A, b in devs]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = []
+    torch.cuda.synchronize()
+    for (A, b), st in zip(devs, streams):
+        sk = sns.sketch_desc("count", 4 * A.shape[1], 7)
+        M = sns.dense(A)
+        o = sns.opts(1, 100, 1e-6)
+        ws = torch.empty(sns.sns_lstsq_workspace_size(sk, M, o), dtype=torch.uint8, device="cuda")
+        x = torch.empty(A.shape[1], dtype=torch.float64, device="cuda")
+        buf = torch.zeros(64, dtype=torch.uint8).pin_memory()
+        info = sns.Info.from_address(buf.data_ptr())
+        outs.append((x, info, buf, ws))
+        sns.sns_lstsq(sk, M, b, x, o, ws, info, st)
+    torch.cuda.synchronize()
+    for (x, info, _, _), (xs, info_s) in zip(outs, solo):
+        assert info.status == 0 and info_s.status == 0
+        assert info.iters == info_s.iters
+        assert torch.equal(x, xs)
