@@ -6,7 +6,10 @@
 //      caller's device memory);
 //   2. set the admitted requests up in one batched launch per kernel
 //      (CountSketch sort and gather, QR, and for refined requests X = R^{-1}
-//      and the LSQR state);
+//      and the LSQR state) on a second stream, so that the set-up (mostly the
+//      QR: one work-group per request and panel step) overlaps the iterations
+//      of step 3; the requests join the batch in the next round, once the
+//      iteration stream has waited for their set-up;
 //   3. advance every refining request by `chunk_iters` LSQR iterations, again
 //      one batched launch per kernel over all of them, and read back which
 //      ones have stopped;
@@ -111,8 +114,10 @@ size_t request_bytes(const sns_problem& p) {
 struct sns_server {
   sns_serve_config cfg{};
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // iterations, finishing, results
+  hipStream_t stream2 = nullptr;  // set-up of admitted requests
   hipEvent_t ev = nullptr;
+  hipEvent_t ev_setup = nullptr;  // the last set-up launched on stream2
   char* pool = nullptr;  // request area (after the reserved part)
   size_t usable = 0;     // bytes of the request area
   // reserved at the start of the pool
@@ -145,7 +150,8 @@ struct sns_server {
   std::thread worker;
 
   void run();
-  sns_status round(std::vector<Req*>& fresh, std::vector<Req*>& refining);
+  sns_status round(std::vector<Req*>& fresh, std::vector<Req*>& pending,
+                   std::vector<Req*>& refining);
   void complete(std::vector<Req*>& fin, sns_status err);
 };
 
@@ -220,22 +226,17 @@ void sns_server::complete(std::vector<Req*>& fin, sns_status err) {
   cv_work.notify_all();
 }
 
-sns_status sns_server::round(std::vector<Req*>& fresh, std::vector<Req*>& refining) {
+sns_status sns_server::round(std::vector<Req*>& fresh, std::vector<Req*>& pending,
+                             std::vector<Req*>& refining) {
   const bool f64 = cfg.dtype == SNS_F64;
   hipStream_t st = stream;
   sns_status s = SNS_OK;
   std::vector<Req*> fin;
-  // -- set-up of the admitted requests
-  if (!fresh.empty()) {
-    ArgTable t(tab_setup);
-    sns::Jobs J;
-    build_setup(t, J, fresh, f64);
-    if (t.bytes() > tab_bytes) return SNS_ERR_OUT_OF_MEMORY;
-    if ((s = t.upload(st)) != SNS_OK) return s;
-    if ((s = sns::run_sketch_jobs(J, st)) != SNS_OK) return s;
-    if ((s = sns::launch_qr_job(J.qr, st)) != SNS_OK) return s;
-    if ((s = sns::launch_lsqr_setup(J.lsqr, st)) != SNS_OK) return s;
-    for (Req* r : fresh) {
+  // -- requests set up during the previous round join (the iteration stream
+  //    waits for their set-up); plain ones are finished
+  if (!pending.empty()) {
+    SNS_HIP_TRY(hipStreamWaitEvent(st, ev_setup, 0));
+    for (Req* r : pending) {
       if (r->p.opts.refine) {
         refining.push_back(r);
       } else {
@@ -244,6 +245,21 @@ sns_status sns_server::round(std::vector<Req*>& fresh, std::vector<Req*>& refini
         fin.push_back(r);
       }
     }
+    pending.clear();
+  }
+  // -- set-up of the admitted requests on the second stream
+  if (!fresh.empty()) {
+    hipStream_t s2 = stream2;
+    ArgTable t(tab_setup);
+    sns::Jobs J;
+    build_setup(t, J, fresh, f64);
+    if (t.bytes() > tab_bytes) return SNS_ERR_OUT_OF_MEMORY;
+    if ((s = t.upload(s2)) != SNS_OK) return s;
+    if ((s = sns::run_sketch_jobs(J, s2)) != SNS_OK) return s;
+    if ((s = sns::launch_qr_job(J.qr, s2)) != SNS_OK) return s;
+    if ((s = sns::launch_lsqr_setup(J.lsqr, s2)) != SNS_OK) return s;
+    SNS_HIP_TRY(hipEventRecord(ev_setup, s2));
+    pending.swap(fresh);
     fresh.clear();
   }
   // -- one chunk of iterations for every refining request
@@ -286,13 +302,15 @@ sns_status sns_server::round(std::vector<Req*>& fresh, std::vector<Req*>& refini
 
 void sns_server::run() {
   (void)hipSetDevice(device);
-  std::vector<Req*> refining;
+  std::vector<Req*> refining, pending;
   for (;;) {
     std::vector<Req*> fresh;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty() || !refining.empty(); });
-      if (stop && queue.empty() && refining.empty()) break;
+      cv_work.wait(lk, [&] {
+        return stop || !queue.empty() || !refining.empty() || !pending.empty();
+      });
+      if (stop && queue.empty() && refining.empty() && pending.empty()) break;
       // admission in arrival order by slot and by workspace footprint
       while (!queue.empty() && admitted < cfg.max_slots) {
         Req* r = queue.front();
@@ -318,7 +336,7 @@ void sns_server::run() {
                                     r->p.x, r->info_dev);
       }
     }
-    if (fresh.empty() && refining.empty()) {
+    if (fresh.empty() && refining.empty() && pending.empty()) {
       // nothing admissible now (the head waits for memory held by nobody
       // cannot happen: requests larger than the pool are refused at submit)
       std::unique_lock<std::mutex> lk(mu);
@@ -326,15 +344,18 @@ void sns_server::run() {
       continue;
     }
     std::vector<Req*> all_inflight = refining;
+    all_inflight.insert(all_inflight.end(), pending.begin(), pending.end());
     all_inflight.insert(all_inflight.end(), fresh.begin(), fresh.end());
-    const sns_status s = round(fresh, refining);
+    const sns_status s = round(fresh, pending, refining);
     if (s != SNS_OK) {
       // fail everything in flight and keep serving the queue
+      (void)hipStreamSynchronize(stream2);
       (void)hipStreamSynchronize(stream);
       std::vector<Req*> fin;
       for (Req* r : all_inflight)
         if (!r->done) fin.push_back(r);
       refining.clear();
+      pending.clear();
       complete(fin, s);
     }
   }
@@ -368,13 +389,17 @@ sns_status sns_serve_create(const sns_serve_config* cfg, sns_server** out) {
   s->alloc = PoolAlloc(s->usable);
   if (hipGetDevice(&s->device) != hipSuccess ||
       hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->stream2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_setup, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&s->flags_host, sizeof(int) * cfg->max_slots, hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&s->infos_host, sizeof(sns_info) * cfg->max_slots,
                     hipHostMallocDefault) != hipSuccess) {
     if (s->flags_host) (void)hipHostFree(s->flags_host);
+    if (s->ev_setup) (void)hipEventDestroy(s->ev_setup);
     if (s->ev) (void)hipEventDestroy(s->ev);
+    if (s->stream2) (void)hipStreamDestroy(s->stream2);
     if (s->stream) (void)hipStreamDestroy(s->stream);
     delete s;
     return SNS_ERR_HIP;
@@ -470,9 +495,13 @@ sns_status sns_serve_destroy(sns_server* srv) {
   if (srv->worker.joinable()) srv->worker.join();
   for (auto& kv : srv->reqs) delete kv.second;
   srv->reqs.clear();
+  (void)hipStreamSynchronize(srv->stream2);
+  (void)hipStreamSynchronize(srv->stream);
   (void)hipHostFree(srv->flags_host);
   (void)hipHostFree(srv->infos_host);
+  (void)hipEventDestroy(srv->ev_setup);
   (void)hipEventDestroy(srv->ev);
+  (void)hipStreamDestroy(srv->stream2);
   (void)hipStreamDestroy(srv->stream);
   delete srv;
   return SNS_OK;
