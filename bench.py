@@ -292,8 +292,8 @@ def main():
                     choices=sorted(WORKLOADS) + [SERVE_WORKLOAD])
     ap.add_argument("--requests", type=int, default=10000, help="serving mix: requests")
     ap.add_argument("--rate", type=float, default=2000.0, help="serving mix: arrivals per second")
-    ap.add_argument("--slots", type=int, default=64, help="serving mix: admitted requests")
-    ap.add_argument("--chunk", type=int, default=4, help="serving mix: iterations per round")
+    ap.add_argument("--slots", type=int, default=128, help="serving mix: admitted requests")
+    ap.add_argument("--chunk", type=int, default=8, help="serving mix: iterations per round")
     ap.add_argument("--baseline-requests", type=int, default=400)
     ap.add_argument("--cpu-requests", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
