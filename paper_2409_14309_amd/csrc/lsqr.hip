@@ -4,7 +4,8 @@
 // named in the paper's solver list).
 //
 // X is formed once per solve (k_tri_inv, fp64 back substitution per column)
-// and applied as matrix-vector products by many work-groups.  LSQR runs on the
+// and applied as matrix-vector products: spread over many work-groups for
+// n > 256, inside one work-group for smaller n (see below).  LSQR runs on the
 // fixed operator A X and the answer is mapped back with the same X,
 // x = x0 + X dy, so x is the least-squares solution of A x = b whatever the
 // rounding in X; X only has to keep A X well conditioned.
@@ -28,7 +29,9 @@
 //
 // Precision: A and the m-vector u are stored in A's dtype; every product and
 // accumulation is fp64, and all n-vectors are fp64.  Once the stop rule
-// holds, a flag in device memory makes the remaining launches return at once.
+// holds, a flag in device memory makes the remaining launches return at once;
+// for a single problem the device also posts the flag to pinned host memory
+// after every iteration, so the host stops enqueuing without a copy.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
