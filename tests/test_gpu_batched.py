@@ -130,12 +130,13 @@ def test_batch_rejects_mixed_dtypes(gpu_lib):
 def test_batch_straddles_fused_step_limit(gpu_lib):
     """Problems with n <= 256 run the LSQR step inside the reduction kernel,
     larger ones in the separate step kernels; one batch holding both kinds
-    matches the solo calls bit for bit, and FP64 results with a fixed
-    iteration count agree with the oracle's SAP-SAS on both sides of the
-    limit."""
+    (and widths near 512) matches the solo calls bit for bit, and FP64
+    results with a fixed iteration count agree with the oracle's SAP-SAS on
+    both sides of the limit."""
     import torch
     sns = gpu_lib
-    mix = [(6000, 256), (6500, 258), (5000, 254), (7000, 300), (4000, 16)]  # rows of 16 bytes
+    mix = [(6000, 256), (6500, 258), (5000, 254), (7000, 300), (4000, 16),  # rows of 16 bytes
+           (8000, 510), (8000, 512), (8500, 514)]
     probs = _problems(torch, dt=np.float64, mix=mix, seed0=1300)
     got = _batch(sns, probs, True, 6, 0.0, True)
     _same(got, _solo(sns, probs, True, 6, 0.0))
@@ -143,7 +144,8 @@ def test_batch_straddles_fused_step_limit(gpu_lib):
         r = OSV.sap_sas(p.A, p.b, "count", seed, d, 6, rtol=0.0)
         assert info.iters == 6
         assert np.linalg.norm(x - r.x) <= 1e-9 * np.linalg.norm(r.x)
-    probs32 = _problems(torch, mix=[(40000, 256), (40000, 260), (20000, 64)], seed0=1400)
+    probs32 = _problems(torch, mix=[(40000, 256), (40000, 260), (20000, 64), (60000, 512),
+                                    (60000, 516)], seed0=1400)
     solo = _solo(sns, probs32, True, 80, 1e-6)
     _same(_batch(sns, probs32, True, 80, 1e-6, True), solo)
     for (p, *_), (x, info) in zip(probs32, solo):

@@ -29,7 +29,8 @@ def _dev(x, torch):
 
 @pytest.mark.parametrize("m,n,d", [(20000, 64, 256), (10007, 200, 800), (5000, 130, 520),
                                    (3000, 2, 8), (120, 20, 80), (40000, 300, 1200),
-                                   (12000, 256, 1024), (12000, 258, 1032)])
+                                   (12000, 256, 1024), (12000, 258, 1032), (12000, 512, 2048),
+                                   (12000, 514, 2056)])
 def test_saa_fp64_fixed_iterations_matches_oracle(gpu_lib, m, n, d):
     import torch
     p = dense_gaussian(m, n, seed=m + n)
