@@ -48,6 +48,9 @@ def test_host_side_argument_checks():
         (sns.Matrix(1000, 10, 0, 0, None, 10, None, None, 0), sk, 1),     # null values
         (sns.Matrix(1000, 10, 1, 0, fake, 10, None, None, 0), sns.Sketch(1, 64, 1), 3),  # gaussian f64
         (sns.Matrix(1000, 10, 0, 0, fake, 10, None, None, 0), sns.Sketch(5, 64, 1), 1),  # bad kind
+        (sns.Matrix(0, 10, 0, 0, fake, 10, None, None, 0), sk, 2),         # m = 0
+        (sns.Matrix(100000, 10, 0, 0, fake, 10, None, None, 0), sns.Sketch(0, 16385, 1), 2),  # d > 16384
+        (sns.Matrix(1000, 10, 0, 0, fake, 10, None, None, 0), sns.Sketch(0, 0, 1), 2),       # d = 0
     ]
     csr = dict(row_ptr=fake, col_idx=fake)
     cases += [
@@ -70,6 +73,15 @@ def test_host_side_argument_checks():
     # workspace too small
     assert lib.sns_sketch_apply(C.byref(sk), C.byref(A), None, C.c_void_p(fake), None, None,
                                 C.c_void_p(fake), 16, None) == 7
+    # the largest sketch the bucket sort takes is accepted; the QR takes d <= 8192
+    Aw = sns.Matrix(100000, 10, 0, 0, fake, 10, None, None, 0)
+    assert lib.sns_sketch_workspace_size(C.byref(sns.Sketch(0, 16384, 1)), C.byref(Aw),
+                                         C.byref(nb)) == 0
+    o0 = sns.opts()
+    assert lib.sns_lstsq_workspace_size(C.byref(sns.Sketch(0, 8192, 1)), C.byref(Aw), C.byref(o0),
+                                        C.byref(nb)) == 0
+    assert lib.sns_lstsq_workspace_size(C.byref(sns.Sketch(0, 8193, 1)), C.byref(Aw), C.byref(o0),
+                                        C.byref(nb)) == 2
     o = sns.opts(refine=1, max_iters=-1)
     assert lib.sns_lstsq(C.byref(sk), C.byref(A), C.c_void_p(fake), C.c_void_p(fake), C.byref(o),
                          C.c_void_p(fake), 1 << 30, None, None) == 1

@@ -122,3 +122,17 @@ def test_sketch_without_b(gpu_lib):
     torch.cuda.synchronize()
     assert Sb is None
     assert np.array_equal(SA.cpu().numpy(), OS.countsketch_apply(A, None, 77, 60)[0])
+
+
+def test_largest_sketch_size(gpu_lib):
+    """d = 16384, the most buckets the sort's LDS histograms take: integer
+    inputs give bit-exact SA and Sb."""
+    import torch
+    m, n, d = 200000, 8, 16384
+    rng = np.random.default_rng(16384)
+    A = rng.integers(-8, 9, size=(m, n)).astype(np.float32)
+    b = rng.integers(-8, 9, size=m).astype(np.float32)
+    SA, Sb = _run(gpu_lib, torch, A, b, d, 11)
+    SAr, Sbr = OS.countsketch_apply(A, b, 11, d)
+    assert np.array_equal(SA.astype(np.float64), SAr)
+    assert np.array_equal(Sb.astype(np.float64), Sbr)
