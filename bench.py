@@ -15,7 +15,10 @@ reports its residual and forward errors against the exact solution built into
 the data.  --solver saa replaces SAP-SAS by SAA-SAS (Y = A R^-1 formed once);
 --zeta Z > 1 uses the sparse sign embedding instead of the CountSketch,
 --sketch hadamard the subsampled randomized Hadamard transform, --d the
-sketch size.
+sketch size.  --workload serve_mix_10000 drives the continuous-batching server
+with 10,000 requests (Poisson arrivals at 2000/s, m = floor(2^U[12,20]),
+n in {16, ..., 256}, d = 4n): open-loop latency percentiles, saturated
+throughput (value) and one-problem-at-a-time baselines.
 
 Prints one JSON line: solves/s (value), p50/p99 step latency, the CountSketch
 pass bandwidth, a roofline record for the dominant kernel (timed with HIP
