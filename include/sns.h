@@ -243,13 +243,14 @@ sns_status sns_lstsq_batched(const sns_problem* probs, int count, void* workspac
 
 /* ------------------------------------------------------------- serving --
  * A server solves submitted problems with continuous batching.  A scheduler
- * thread owns a HIP stream and works in rounds: it admits waiting requests
+ * thread owns two HIP streams and works in rounds: it admits waiting requests
  * in arrival order while a slot is free and the request's workspace fits in
  * the pool (admission by device-memory footprint), sets the admitted ones up
- * together (sketch, QR, X = R^{-1}; one batched launch per kernel), advances
- * every admitted request by a chunk of refinement iterations in one batched
- * launch per kernel, and retires the requests whose stop rule has fired.
- * Requests that arrive while others run join at the next round, so their
+ * together on the second stream (sketch, QR, X = R^{-1}; one batched launch
+ * per kernel) while the first advances every request set up in an earlier
+ * round by a chunk of refinement iterations (one batched launch per kernel),
+ * and retires the requests whose stop rule has fired.  A request joins the
+ * iterating batch in the round after its set-up, behind an event, so its
  * work shares launches with the running ones.  Each request's arithmetic is
  * the one sns_lstsq does for it alone: x and info are bit-identical to a
  * solo call whatever else is in flight. */
