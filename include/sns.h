@@ -203,6 +203,13 @@ sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
  * its workspace holds Y.
  * A may be CSR with refine = 0 (plain sketch-and-solve); refinement streams
  * dense rows and returns SNS_ERR_DTYPE for CSR.
+ * With refinement and rtol > 0 the call holds the host thread while the
+ * iterations run: the device posts its stop flag to pinned host memory after
+ * each iteration, the host keeps at most two iterations enqueued ahead of the
+ * last flag it has read, and returns once it has enqueued the final update
+ * (the stream then completes the solve).  With rtol = 0, or while the stream
+ * is being captured, all max_iters + 1 iterations are enqueued at once and the
+ * call returns without waiting.
  * Errors: as sns_sketch_apply, plus SNS_ERR_INVALID_ARG for refine outside
  * 0..2, max_iters < 0 or rtol < 0. */
 sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, double* x,
