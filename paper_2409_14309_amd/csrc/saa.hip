@@ -27,8 +27,13 @@ __global__ __launch_bounds__(kYThreads, 2) void k_form_y(const T* __restrict__ A
   __shared__ __attribute__((aligned(16))) T As[kYK][kYT + kYPad];  // A's dtype, widened when read
   __shared__ __attribute__((aligned(16))) double Xs[kYK][kYT + kYPad];
   const int t = threadIdx.x;
-  const int cj = (int)(blockIdx.x % (unsigned)ctn);
-  const int64_t i0 = (int64_t)(blockIdx.x / (unsigned)ctn) * kYT;
+  // Work-groups are handed to the 8 XCDs in turn; renumber them so that the
+  // column tiles of one row tile, which read the same rows of A, run on one
+  // XCD and share those rows in its L2.
+  const unsigned nwg = gridDim.x, h = blockIdx.x;
+  const unsigned L = (nwg % 8u == 0u) ? (h % 8u) * (nwg / 8u) + h / 8u : h;
+  const int cj = (int)(L % (unsigned)ctn);
+  const int64_t i0 = (int64_t)(L / (unsigned)ctn) * kYT;
   const int j0 = cj * kYT;
   const int kend = j0 + kYT < n ? j0 + kYT : n;  // X[k][j] = 0 for k > j
   const int nk = (kend + kYK - 1) / kYK;
