@@ -189,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrArgs* __restrict__ P, M
 // W = V^T C in registers (independent loads, no barriers); W is reduced over
 // the group through LDS in a fixed order and multiplied by T^T.  Sweep 2 re-reads V and
 // C and applies the update.
-constexpr int kTrailThreads = 256;
+constexpr int kTrailThreads = 512;
 
 // Columns per trailing work item.  It depends only on the problem's own n
 // (the reduction order, hence the rounding, follows it): one column per
