@@ -556,7 +556,7 @@ __global__ void k_lsqr_init(const LsqrArgs* __restrict__ P, Map mp) {
 // X = R^{-1}: item j solves R x = e_j on the leading (j+1) x (j+1) block by
 // back substitution and writes column j of X (column-major Xc and row-major
 // Xr; X is upper triangular).
-constexpr int kInvThreads = 64;
+constexpr int kInvThreads = 256;
 __global__ __launch_bounds__(kInvThreads) void k_tri_inv(const LsqrArgs* __restrict__ P, Map mp) {
   extern __shared__ double sh[];
   const uint32_t it = blockIdx.x;
@@ -578,7 +578,7 @@ __global__ __launch_bounds__(kInvThreads) void k_tri_inv(const LsqrArgs* __restr
 }
 
 constexpr int kGemvThreads = 256;
-constexpr int kGemvRows = 16;  // rows per work item (4 per wave)
+constexpr int kGemvRows = 8;   // rows per work item (2 per wave)
 
 // Dot product of row i of a triangular matrix stored row-contiguously
 // (M[i * n + j]) with vec over j in [j0, j1), by one wave; all lanes get it.
