@@ -577,8 +577,8 @@ __global__ __launch_bounds__(kInvThreads) void k_tri_inv(const LsqrArgs* __restr
   }
 }
 
-constexpr int kGemvThreads = 256;
-constexpr int kGemvRows = 8;   // rows per work item (2 per wave)
+constexpr int kGemvThreads = 512;
+constexpr int kGemvRows = 8;   // rows per work item (one per wave)
 
 // Dot product of row i of a triangular matrix stored row-contiguously
 // (M[i * n + j]) with vec over j in [j0, j1), by one wave; all lanes get it.
