@@ -3,7 +3,7 @@
 //
 // Layout: the working copy M is column-major with leading dimension d.
 // Blocked right-looking algorithm: for each panel of nb columns,
-//   k_qr_panel    one work-group of 512 threads holds the panel rows in
+//   k_qr_panel    one work-group (256 or 512 threads) holds the panel rows in
 //                 registers and factors it column by column.  Each column
 //                 needs one work-group reduction, which yields the norm, the
 //                 products of the column with the remaining panel columns
@@ -485,8 +485,8 @@ sns_status launch_qr_job(const QrJob& j, hipStream_t st) {
   for (const QrJob::Cls& c : j.cls) {
     switch (c.cfg) {
       // panel configurations: rows per thread, panel width, threads (d <= NT * MAXR)
-      case 0: run_panels_cb<1, 16, 512>(c, st); break;
-      case 1: run_panels_cb<2, 16, 512>(c, st); break;
+      case 0: run_panels_cb<2, 16, 256>(c, st); break;
+      case 1: run_panels_cb<4, 16, 256>(c, st); break;
       case 2: run_panels_cb<4, 16, 512>(c, st); break;
       case 3: run_panels_cb<8, 8, 512>(c, st); break;
       default: run_panels_cb<16, 4, 512>(c, st); break;
