@@ -96,7 +96,19 @@ __global__ void k_scan_segments(const SortArgs* __restrict__ P, Map mp) {
   if (k >= a.d) return;
   const int64_t w0 = s * a.seg, w1 = min(a.nwb, w0 + a.seg);
   uint32_t run = 0;
-  for (int64_t wb = w0; wb < w1; ++wb) {
+  int64_t wb = w0;
+  // 16 counts loaded before any is overwritten: one memory round trip per 16
+  for (; wb + 16 <= w1; wb += 16) {
+    uint32_t c[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) c[u] = a.counts[(wb + u) * a.d + k];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      a.counts[(wb + u) * a.d + k] = run;
+      run += c[u];
+    }
+  }
+  for (; wb < w1; ++wb) {
     const uint32_t c = a.counts[wb * a.d + k];
     a.counts[wb * a.d + k] = run;
     run += c;
@@ -115,7 +127,18 @@ __device__ __forceinline__ void scan_buckets_item(const SortArgs& a, uint32_t* w
   uint32_t local = 0;
   for (uint32_t k = k0; k < k1; ++k) {
     uint32_t run = 0;
-    for (int64_t s = 0; s < a.nseg; ++s) {
+    int64_t s = 0;
+    for (; s + 16 <= a.nseg; s += 16) {  // 16 loads in flight before the stores
+      uint32_t c[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) c[u] = a.segtot[(s + u) * d + k];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        a.segtot[(s + u) * d + k] = run;
+        run += c[u];
+      }
+    }
+    for (; s < a.nseg; ++s) {
       const uint32_t c = a.segtot[s * d + k];
       a.segtot[s * d + k] = run;
       run += c;
