@@ -85,15 +85,15 @@ KERNEL_SOURCES = {
 }
 
 
-def measured_traffic(kernel: str, src_hash: str):
+def measured_traffic(kernel: str, src_hash: str, workload):
     """HBM bytes per launch from the committed counter runs, if they were taken
-    on the current kernel source; else None."""
+    on the current kernel source and on this exact workload; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(p):
+    if workload is None or not os.path.exists(p):
         return None
     with open(p) as f:
         rec = json.load(f).get(kernel)
-    if not rec or rec.get("source_hash") != src_hash:
+    if not rec or rec.get("source_hash") != src_hash or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_launch")
 
@@ -441,13 +441,19 @@ def main():
     # multiply-adds per row of A, on the vector ALUs
     alu_flops_per = {"form_y": float(m) * n * (n + 1)}
 
+    # counters were taken on the named workloads as they stand: any override
+    # of the shape, sketch or solver leaves traffic unmeasured
+    traffic_workload = (args.workload if not (args.m or args.d or args.sketch or args.zeta > 1
+                                             or args.solver != "sap") else None)
+
     def roofline(kname):
         cnt, tot, avg_us = kt[kname]
         if kname in bytes_per:
             ach = bytes_per[kname] / (avg_us * 1e-6) / 1e9
             return {"kernel": kname, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
-                    "traffic": (measured_traffic(kname, kernel_source_hash(*KERNEL_SOURCES[kname]))
+                    "traffic": (measured_traffic(kname, kernel_source_hash(*KERNEL_SOURCES[kname]),
+                                                 traffic_workload)
                                 if kname in KERNEL_SOURCES else None),
                     "bytes_per_launch": bytes_per[kname], "avg_launch_us": avg_us, "launches": cnt}
         if kname in flops_per:

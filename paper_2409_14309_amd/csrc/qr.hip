@@ -192,9 +192,10 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrArgs* __restrict__ P, M
 constexpr int kTrailThreads = 512;
 
 // Columns per trailing work item.  It depends only on the problem's own n
-// (the reduction order, hence the rounding, follows it): one column per
-// work-group keeps hundreds of work-groups busy for the n of the workloads.
-int trail_cb(int64_t n) { return n > 2048 ? 2 : 1; }
+// (the reduction order, hence the rounding, follows it).  Two columns per
+// work-group halve the reads of V per column; below n = 384 the halved
+// number of work-groups no longer fills the chip and one column is faster.
+int trail_cb(int64_t n) { return n >= 384 ? 2 : 1; }
 
 template <int NB>
 __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t d, int64_t j0,
@@ -205,8 +206,11 @@ __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t 
 }
 
 // One work item per CB trailing columns; a problem owns ceil(n / CB) items,
-// of which the first ceil(ntr / CB) have columns at step j0.
-template <int NB, int CB>
+// of which the first ceil(ntr / CB) have columns at step j0.  Thread t owns
+// rows j0 + t + NT r, r < MAXR (d <= MAXR NT): its entries of V and of its
+// columns stay in registers from the first sweep to the second, so V is read
+// from memory once per work-group.
+template <int MAXR, int NB, int CB>
 __global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(const QrArgs* __restrict__ P,
                                                                Map mp, int64_t j0) {
   constexpr int NT = kTrailThreads, NV = NB * CB;
@@ -234,19 +238,22 @@ __global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(const QrArgs* __r
     jc[c] = jc0 + c;
     ok[c] = jc[c] <= n;
   }
+  double v[MAXR][NB], cv[MAXR][CB];
   double acc[NV];
 #pragma unroll
   for (int e = 0; e < NV; ++e) acc[e] = 0.0;
-  for (int64_t i = j0 + t; i < d; i += NT) {
-    double v[NB], cv[CB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) v[q] = v_entry<NB>(M, d, j0, q, nbw, i);
+  for (int r = 0; r < MAXR; ++r) {
+    const int64_t i = j0 + t + (int64_t)NT * r;
+    const bool in = i < d;
 #pragma unroll
-    for (int c = 0; c < CB; ++c) cv[c] = ok[c] ? M[jc[c] * d + i] : 0.0;
+    for (int q = 0; q < NB; ++q) v[r][q] = in ? v_entry<NB>(M, d, j0, q, nbw, i) : 0.0;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) cv[r][c] = (in && ok[c]) ? M[jc[c] * d + i] : 0.0;
 #pragma unroll
     for (int q = 0; q < NB; ++q)
 #pragma unroll
-      for (int c = 0; c < CB; ++c) acc[q * CB + c] = fma(v[q], cv[c], acc[q * CB + c]);
+      for (int c = 0; c < CB; ++c) acc[q * CB + c] = fma(v[r][q], cv[r][c], acc[q * CB + c]);
   }
   block_reduce_multi<NV, NT>(acc, red, W);
   // W' = T^T W with T upper triangular (column-major NB x NB)
@@ -260,17 +267,17 @@ __global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(const QrArgs* __r
   double wt[NV];
 #pragma unroll
   for (int e = 0; e < NV; ++e) wt[e] = Wt[e];
-  for (int64_t i = j0 + t; i < d; i += NT) {
-    double v[NB];
 #pragma unroll
-    for (int q = 0; q < NB; ++q) v[q] = v_entry<NB>(M, d, j0, q, nbw, i);
+  for (int r = 0; r < MAXR; ++r) {
+    const int64_t i = j0 + t + (int64_t)NT * r;
+    if (i >= d) continue;
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
       if (!ok[c]) continue;
       double s = 0.0;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) s = fma(v[q], wt[q * CB + c], s);
-      M[jc[c] * d + i] -= s;
+      for (int q = 0; q < NB; ++q) s = fma(v[r][q], wt[q * CB + c], s);
+      M[jc[c] * d + i] = cv[r][c] - s;
     }
   }
 }
@@ -375,11 +382,13 @@ int qr_cfg(int64_t d) {
 
 template <int MAXR, int NB, int NT, int CB>
 void run_panels(const QrJob::Cls& c, hipStream_t st) {
+  // rows per thread of the trailing update (d <= MAXR NT, the panel's bound)
+  constexpr int TR = (MAXR * NT + kTrailThreads - 1) / kTrailThreads;
   for (int64_t j0 = 0; j0 < c.maxn; j0 += NB) {
     SNS_LAUNCH("qr_panel", (k_qr_panel<MAXR, NB, NT>), dim3(grid_for((uint32_t)c.count)),
                dim3(NT), 0, st, c.args, c.mone, j0);
     if (c.ntrail)
-      SNS_LAUNCH("qr_trailing", (k_qr_trailing<NB, CB>), dim3(grid_for(c.ntrail)),
+      SNS_LAUNCH("qr_trailing", (k_qr_trailing<TR, NB, CB>), dim3(grid_for(c.ntrail)),
                  dim3(kTrailThreads), 0, st, c.args, c.mtrail, j0);
   }
 }
