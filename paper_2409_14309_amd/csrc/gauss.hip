@@ -96,11 +96,7 @@ struct GaussTable {
 // so that the 16-byte stores of one wave (rows 4 l + c, l = lane) spread over
 // all banks while the fragment reads (32 consecutive rows, one chunk) stay
 // conflict free.
-#ifndef SNS_GAUSS_SWZ64
 __device__ __forceinline__ int aswz(int r) { return ((r >> 4) & 1) | (((r >> 3) & 1) << 1); }
-#else
-__device__ __forceinline__ int aswz(int r) { return ((r >> 5) & 1) | (((r >> 4) & 1) << 1); }
-#endif
 
 __device__ __forceinline__ __bf16 bits_to_bf16(unsigned short u) {
   return __builtin_bit_cast(__bf16, u);
