@@ -339,7 +339,9 @@ def main():
     ap.add_argument("--m", type=int, default=0, help="override the workload's row count")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--max-iters", type=int, default=100)
-    ap.add_argument("--cpu-rows", type=int, default=1 << 19)
+    ap.add_argument("--cpu-rows", type=int, default=1 << 22,
+                    help="rows of A the CPU oracle solves (capped at m; 100,000 on the FP64 "
+                         "Sec. 3.1 family); its time is scaled to the full m")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--zeta", type=int, default=1,
                     help="CountSketch workloads: > 1 uses the sparse sign embedding with zeta "
