@@ -2,7 +2,9 @@
 benchmark times: the 4,194,304 x 256 FP32 ill-conditioned problem with the
 CountSketch (d = 1024, seed 42), the 262,144 x 512 FP32 problem with the
 Gaussian sketch (d = 2048), and the Sec. 3.1 family at 1,000,000 x 1000 FP64
-(d = 4000); every solve is SAP-SAS or SAA-SAS to rtol 1e-6.
+(d = 4000), each solved by SAP-SAS or SAA-SAS to rtol 1e-6; and the
+16,777,216 x 1000 CSR problem (d = 4000) by plain sketch-and-solve, against
+the oracle's sketch-and-solve element by element.
 
 The oracle recomputes sampled buckets of SA one by one (every row the hash
 sends to the bucket, signed, summed in fp64) and all of Sb; the refined
@@ -15,7 +17,8 @@ import pytest
 
 from oracle import sketch as OS
 import workloads
-from workloads import dense_ill_conditioned, dense_scaled_columns
+from oracle import solve as OSV
+from workloads import dense_ill_conditioned, dense_scaled_columns, sparse_csr
 
 # generating the data (about 8 s) and the host QR of [A | b] (about a minute)
 # dominate the time
@@ -125,3 +128,28 @@ def test_paper_family_full_size(gpu_lib, paper_problem, kind, refine, zeta):
     # sigma_min = 1e-10 = beta and ||x|| = 1, so ||dx|| <= ||A dx|| / sigma_min
     # gives FE <= RE
     assert fe <= 1e-6, (re, fe)
+
+
+@pytest.fixture(scope="module")
+def csr_problem(gpu_lib):
+    """16,777,216 x 1000 CSR (d = 4000) and the oracle's sketch-and-solve x0."""
+    p = sparse_csr(1 << 24, 1000, seed=1002)
+    return p, OSV.sketch_and_solve(p.A, p.b, "count", SEED, 4000).x
+
+
+@pytest.mark.parametrize("accum_fp64,tol", [(False, 1e-4), (True, 1e-5)])
+def test_csr_full_size_plain_solve(gpu_lib, csr_problem, accum_fp64, tol):
+    """Plain sketch-and-solve at full size.  kappa(SA) is about 4, so x0
+    moves by at most a few times the sketch's relative error: FP32 partial
+    sums (the benchmark's setting) or FP64 ones, SA rounded to FP32 either
+    way."""
+    import torch
+    p, xr = csr_problem
+    A = p.A
+    M = gpu_lib.CsrMatrix(_dev(A.indptr.astype(np.int32), torch), _dev(A.indices.astype(np.int32), torch),
+                          _dev(A.data, torch), A.shape)
+    x, info = gpu_lib.lstsq(M, _dev(p.b, torch), "count", 4000, SEED, accum_fp64=accum_fp64)
+    assert info.status == 0
+    xg = x.cpu().numpy()
+    err = np.linalg.norm(xg - xr) / np.linalg.norm(xr)
+    assert err <= tol, err
