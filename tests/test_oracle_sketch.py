@@ -18,6 +18,9 @@ are uniform and signs balanced; E||Sx||^2 = ||x||^2 (statistical).
 Gaussian table: symmetric, monotone, every entry the bfloat16 rounding of the
 normal quantile computed independently by bisection on math.erfc; bfloat16
 rounding agrees with torch's float32 -> bfloat16 conversion.
+Gaussian apply: the d^{-1/2} scale by E[S^T S] = var(T) I over seeds (a 1/d
+scale or none fails it); A and b rounded to bfloat16 exactly as torch rounds
+them, and b sketched as one more column of A.
 """
 import math
 
@@ -215,6 +218,46 @@ def test_gaussian_sketch_isotropy():
     assert np.max(np.abs(np.diag(C) - var)) < 6 * var * math.sqrt(2.0 / d)
     off = C - np.diag(np.diag(C))
     assert np.max(np.abs(off)) < 6 * var / math.sqrt(d)
+
+
+def test_gaussian_apply_scale_by_expected_gram():
+    # Sec. 1.2.1: S = d^{-1/2} G, so E[S^T S] = var(T) I.  Sketching the
+    # identity (exact in bf16) returns S; its Gram matrix averaged over seeds
+    # must show var(T) on the diagonal.  A 1/d scale or no scale misses it by
+    # a factor d or 1/d.
+    m, d, seeds = 24, 64, 120
+    var = float(np.mean(S.gaussian_table() ** 2))
+    acc = np.zeros((m, m))
+    for sd in range(seeds):
+        SA, _ = S.gaussian_apply(np.eye(m), None, 1000 + sd, d)
+        acc += SA.T @ SA
+    acc /= seeds
+    # each diagonal entry is a mean of seeds * d squared table values / d
+    sd_diag = var * math.sqrt(2.0 / (d * seeds))
+    assert np.max(np.abs(np.diag(acc) - var)) < 6 * sd_diag
+    off = acc - np.diag(np.diag(acc))
+    assert np.max(np.abs(off)) < 6 * var / math.sqrt(d * seeds)
+
+
+def test_gaussian_apply_rounds_a_and_b_like_torch_bfloat16():
+    # The product is taken with bf16(A) and bf16(b), round to nearest even;
+    # torch's float32 -> bfloat16 conversion is an independent rounding.
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(17)
+    m, n, d, seed = 300, 5, 32, 77
+    A = rng.standard_normal((m, n)).astype(np.float32).astype(np.float64)
+    b = rng.standard_normal(m).astype(np.float32).astype(np.float64)
+    SA, Sb = S.gaussian_apply(A, b, seed, d)
+    G = S.gaussian_matrix(seed, d, m)
+    Ab = torch.from_numpy(A.astype(np.float32)).bfloat16().double().numpy()
+    bb = torch.from_numpy(b.astype(np.float32)).bfloat16().double().numpy()
+    np.testing.assert_allclose(SA, (G @ Ab) / math.sqrt(d), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(Sb, (G @ bb) / math.sqrt(d), rtol=0, atol=1e-12)
+    # b is treated like a column of A: [A | b] sketched together gives Sb
+    SAb, _ = S.gaussian_apply(np.column_stack([A, b]), None, seed, d)
+    assert np.array_equal(SAb[:, n], Sb)
+    # and the rounding matters at this scale (unrounded b differs)
+    assert np.max(np.abs(Sb - (G @ b) / math.sqrt(d))) > 1e-6
 
 
 # ------------------------------------------------------ sparse sign ----

@@ -21,6 +21,7 @@ import math
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 from scipy.sparse.linalg import LinearOperator, lsqr as scipy_lsqr
 
 from oracle import lsqr as L
@@ -127,6 +128,33 @@ def test_metrics_pythagoras_identity():
     assert abs((1 + m["SUB"]) ** 2 - (1 + m["RE"] ** 2)) < 1e-10
     m0 = MT.metrics(p.A, p.b, xs, xs)
     assert m0["FE"] == 0.0 and m0["RE"] == 0.0 and m0["eta"] < 1e-12
+
+
+def test_metrics_closed_form_on_embedded_identity():
+    # A = [I_n; 0], b = [c; r]: then x* = c, A^T (b - A x) = c - x,
+    # ||A||_F = sqrt(n) and ||b - A x||^2 = ||c - x||^2 + ||r||^2, so every
+    # metric has a closed form at any x.
+    rng = np.random.default_rng(31)
+    m, n = 40, 6
+    A = np.zeros((m, n))
+    A[:n, :n] = np.eye(n)
+    c = rng.standard_normal(n)
+    r = rng.standard_normal(m - n)
+    b = np.concatenate([c, r])
+    x = c + 0.3 * rng.standard_normal(n)
+    xs = MT.lstsq_exact(A, b)
+    np.testing.assert_allclose(xs, c, rtol=0, atol=1e-14)
+    met = MT.metrics(A, b, x, c)
+    e, nr = np.linalg.norm(c - x), np.linalg.norm(r)
+    res = math.sqrt(e * e + nr * nr)
+    assert abs(met["FE"] - e / np.linalg.norm(c)) < 1e-14
+    assert abs(met["RE"] - e / nr) < 1e-14
+    assert abs(met["SUB"] - (res / nr - 1.0)) < 1e-14
+    assert abs(met["eta"] - e / (math.sqrt(n) * res)) < 1e-14
+    # the same through a sparse A
+    mets = MT.metrics(sp.csr_matrix(A), b, x, c)
+    for k in met:
+        assert abs(mets[k] - met[k]) < 1e-14
 
 
 def test_gaussian_sas_closed_form_suboptimality():
