@@ -272,52 +272,6 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
-def copy_calibration(nbytes: int):
-    """Five device-to-device copies of a known size: under rocprofv3 --pmc
-    their FETCH_SIZE / WRITE_SIZE readings convert the counters of the
-    library's kernels into bytes."""
-    import torch
-    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    for _ in range(5):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
-
-
-def read_probe(nbytes: int, reps: int = 10):
-    """Plain streaming reads of one device buffer over a few launch shapes:
-    the read rate the HBM-bound kernels can reach here, next to the 8 TB/s
-    peak.  Prints one JSON line with every shape's rate and the best."""
-    import torch
-    import paper_2409_14309_amd as sns
-    sns.load()
-    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    out = torch.zeros(65536, dtype=torch.float32, device="cuda")
-    stream = torch.cuda.current_stream()
-    rates = {}
-    for threads in (256, 1024):
-        for groups in (1024, 2048, 4096, 8192):
-            for unroll in (1, 4):
-                for nt in (False, True):
-                    for _ in range(2):
-                        sns.sns_read_probe(buf, groups, threads, unroll, nt, out, stream)
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    for _ in range(reps):
-                        sns.sns_read_probe(buf, groups, threads, unroll, nt, out, stream)
-                    e1.record(stream)
-                    e1.synchronize()
-                    gbps = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
-                    rates[f"t{threads}_g{groups}_u{unroll}_{'nt' if nt else 'plain'}"] = round(gbps, 1)
-    best = max(rates, key=rates.get)
-    print(json.dumps({"read_probe_bytes": nbytes, "reps": reps, "best": best,
-                      "best_GBps": rates[best], "frac_peak": round(rates[best] / HBM_PEAK_GBPS, 4),
-                      "rates_GBps": rates}), flush=True)
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,11 +285,6 @@ def main():
     ap.add_argument("--chunk", type=int, default=8, help="serving mix: iterations per round")
     ap.add_argument("--baseline-requests", type=int, default=400)
     ap.add_argument("--cpu-requests", type=int, default=20)
-    ap.add_argument("--read-probe", type=int, default=0, metavar="BYTES",
-                    help="time plain streaming reads of a BYTES buffer over a few launch "
-                         "shapes (the practical ceiling of the HBM-bound kernels) and exit")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only run 5 plain device copies of BYTES bytes (scales HBM counters)")
     ap.add_argument("--m", type=int, default=0, help="override the workload's row count")
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--max-iters", type=int, default=100)
@@ -360,12 +309,6 @@ def main():
 
     if args.workload == SERVE_WORKLOAD:
         serve_main(args)
-        return
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if args.read_probe:
-        read_probe(args.read_probe)
         return
 
     import numpy as np

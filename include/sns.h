@@ -355,19 +355,6 @@ void sns_timing_select(const char* names);
 void sns_timing_reset(void);
 int sns_timing_summary(char* buf, size_t len);
 
-/* Bandwidth probe (measurement support, not part of the method): one plain
- * streaming read of `bytes` at `buf` (device, 16-byte aligned, bytes a
- * multiple of 16) by `groups` work-groups of `threads` threads (256, 512 or
- * 1024), grid-stride over 16-byte vectors with `unroll` (1 or 4) loads in
- * flight per thread, nontemporal if `nontemporal` != 0.  It gives the read
- * rate the HBM-bound kernels can reach on this device; the caller times it
- * with events on `stream`.  `out` (device, `groups` floats) is written only
- * in a case no finite input reaches.  Asynchronous.
- * Errors: SNS_ERR_INVALID_ARG for null pointers or a launch shape outside
- * those ranges (groups 1..65536), SNS_ERR_SHAPE for a misaligned buffer or
- * size. */
-sns_status sns_read_probe(const void* buf, size_t bytes, int groups, int threads, int unroll,
-                          int nontemporal, float* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -116,8 +116,6 @@ _SIGS = {
     "sns_timing_select": (None, [C.c_char_p]),
     "sns_timing_reset": (None, []),
     "sns_timing_summary": (C.c_int, [C.c_char_p, C.c_size_t]),
-    "sns_read_probe": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_int, C.c_int,
-                                 C.c_void_p, C.c_void_p]),
 }
 
 
@@ -399,12 +397,3 @@ def sns_timing_summary() -> dict:
         name, cnt, tot, avg = line.split()
         out[name] = (int(cnt), float(tot), float(avg))
     return out
-
-
-def sns_read_probe(buf, groups: int = 2048, threads: int = 1024, unroll: int = 1,
-                   nontemporal: bool = False, out=None, stream=None):
-    """One streaming read of the device tensor buf (asynchronous); out is a
-    device buffer of at least `groups` floats."""
-    _check(load().sns_read_probe(_ptr(buf), buf.numel() * buf.element_size(), groups, threads,
-                                 unroll, 1 if nontemporal else 0, _ptr(out), _stream(stream)),
-           "sns_read_probe")

@@ -182,62 +182,3 @@ int sns_timing_summary(char* buf, size_t len) {
 }
 
 }  // extern "C"
-
-// ------------------------------------------------------- bandwidth probe ----
-// The practical ceiling of the HBM-bound kernels: one streaming read of a
-// device buffer, grid-stride over 16-byte vectors with U loads in flight per
-// thread, plain or nontemporal.  The sum is stored only when it equals a
-// value no finite input of this size reaches, so the loads stay live without
-// a store per work-group.
-namespace sns {
-namespace {
-
-template <int U, bool NT>
-__global__ void k_read_probe(const float* __restrict__ a, size_t nvec, float* __restrict__ out) {
-  typedef float F4 __attribute__((ext_vector_type(4)));
-  const F4* __restrict__ p = reinterpret_cast<const F4*>(a);
-  F4 acc = {0.f, 0.f, 0.f, 0.f};
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i + (U - 1) * stride < nvec; i += U * stride) {
-    F4 v[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = NT ? __builtin_nontemporal_load(p + i + u * stride) : p[i + u * stride];
-#pragma unroll
-    for (int u = 0; u < U; ++u) acc += v[u];
-  }
-  for (; i < nvec; i += stride) acc += NT ? __builtin_nontemporal_load(p + i) : p[i];
-  const float s = (acc.x + acc.y) + (acc.z + acc.w);
-  if (s == -3.0e38f) out[blockIdx.x] = s;
-}
-
-template <int U, bool NT>
-void launch_read_probe(const float* a, size_t nvec, int groups, int threads, float* out,
-                       hipStream_t st) {
-  SNS_LAUNCH("read_probe", (k_read_probe<U, NT>), dim3(groups), dim3(threads), 0, st, a, nvec, out);
-}
-
-}  // namespace
-}  // namespace sns
-
-extern "C" sns_status sns_read_probe(const void* buf, size_t bytes, int groups, int threads,
-                                     int unroll, int nontemporal, float* out, void* stream) {
-  if (!buf || !out) return SNS_ERR_INVALID_ARG;
-  if (groups < 1 || groups > 65536 || (threads != 256 && threads != 512 && threads != 1024) ||
-      (unroll != 1 && unroll != 4))
-    return SNS_ERR_INVALID_ARG;
-  if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(buf) % 16 != 0) return SNS_ERR_SHAPE;
-  if (bytes == 0) return SNS_OK;
-  const float* a = static_cast<const float*>(buf);
-  const size_t nvec = bytes / 16;
-  hipStream_t st = (hipStream_t)stream;
-  if (unroll == 4) {
-    if (nontemporal) sns::launch_read_probe<4, true>(a, nvec, groups, threads, out, st);
-    else sns::launch_read_probe<4, false>(a, nvec, groups, threads, out, st);
-  } else {
-    if (nontemporal) sns::launch_read_probe<1, true>(a, nvec, groups, threads, out, st);
-    else sns::launch_read_probe<1, false>(a, nvec, groups, threads, out, st);
-  }
-  SNS_HIP_TRY(hipGetLastError());
-  return SNS_OK;
-}

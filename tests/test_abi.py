@@ -124,21 +124,6 @@ def test_host_side_argument_checks():
     assert lib.sns_lstsq_batched_workspace_size(probs, 1, C.byref(nb)) == 3
 
 
-def test_read_probe_argument_checks():
-    import paper_2409_14309_amd as sns
-    lib = sns.load()
-    fake = 0x1000  # never dereferenced: every call below fails validation first
-    assert lib.sns_read_probe(None, 1024, 64, 256, 1, 0, fake, None) == 1       # null buffer
-    assert lib.sns_read_probe(fake, 1024, 64, 256, 1, 0, None, None) == 1       # null out
-    assert lib.sns_read_probe(fake, 1024, 0, 256, 1, 0, fake, None) == 1        # no groups
-    assert lib.sns_read_probe(fake, 1024, 65537, 256, 1, 0, fake, None) == 1    # too many groups
-    assert lib.sns_read_probe(fake, 1024, 64, 128, 1, 0, fake, None) == 1       # block size
-    assert lib.sns_read_probe(fake, 1024, 64, 256, 2, 0, fake, None) == 1       # unroll
-    assert lib.sns_read_probe(fake, 1000, 64, 256, 1, 0, fake, None) == 2       # size % 16
-    assert lib.sns_read_probe(fake + 4, 1024, 64, 256, 1, 0, fake, None) == 2   # misaligned
-    assert lib.sns_read_probe(fake, 0, 64, 256, 1, 0, fake, None) == 0          # nothing to read
-
-
 def test_device_gaussian_table_matches_oracle_bits():
     """The library builds its own table (host inverse normal + bf16 rounding);
     it must equal the oracle's table bit for bit."""
