@@ -287,8 +287,11 @@ typedef struct {
 sns_status sns_serve_create(const sns_serve_config* cfg, sns_server** out);
 
 /* Queue one problem (same rules as sns_lstsq: dense CountSketch, A, b and x in
- * device memory, written before the call; they must stay valid until the
- * request completes).  *ticket identifies the request.  Errors: as sns_lstsq
+ * device memory; they must stay valid until the request completes).  The
+ * server's streams wait on no caller stream: every write to A, b or x that
+ * the caller enqueued must be complete when this call is made (synchronise
+ * the stream it went to first), and x must not be read before sns_serve_poll
+ * or sns_serve_wait reports the request done.  *ticket identifies the request.  Errors: as sns_lstsq
  * (checked now), SNS_ERR_DTYPE (dtype differs from the server's),
  * SNS_ERR_OUT_OF_MEMORY (workspace larger than the pool), SNS_ERR_QUEUE_FULL. */
 sns_status sns_serve_submit(sns_server* srv, const sns_problem* req, uint64_t* ticket);

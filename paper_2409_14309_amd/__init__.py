@@ -30,6 +30,61 @@ class CsrMatrix:
         self.dtype, self.device = values.dtype, values.device
 
 
+def check_args(A, b=None, x=None, need_cuda: bool = True):
+    """Reject tensors the kernels would misread, before anything is launched:
+    every tensor on one device (a GPU unless need_cuda is False), A dense
+    (2-D float32/float64 with unit column stride and row stride >= n) or a
+    CsrMatrix (contiguous int32 row_ptr of m+1 and col_idx of nnz entries,
+    contiguous float32/float64 values), b contiguous with m entries of A's
+    dtype, x contiguous float64 with n entries.  Raises ValueError."""
+    import torch
+    tensors = []
+    if isinstance(A, CsrMatrix):
+        m, n = A.shape
+        for name, t, dt in (("row_ptr", A.row_ptr, torch.int32), ("col_idx", A.col_idx, torch.int32)):
+            if not isinstance(t, torch.Tensor) or t.dtype != dt or not t.is_contiguous():
+                raise ValueError(f"CSR {name} must be a contiguous int32 tensor")
+        if A.row_ptr.numel() != m + 1:
+            raise ValueError(f"CSR row_ptr has {A.row_ptr.numel()} entries, expected m + 1 = {m + 1}")
+        v = A.values
+        if not isinstance(v, torch.Tensor) or v.dtype not in (torch.float32, torch.float64) \
+                or not v.is_contiguous():
+            raise ValueError("CSR values must be a contiguous float32 or float64 tensor")
+        if A.col_idx.numel() != v.numel():
+            raise ValueError("CSR col_idx and values must have the same number of entries")
+        tensors += [A.row_ptr, A.col_idx, v]
+        dtype = v.dtype
+    else:
+        if not isinstance(A, torch.Tensor) or A.dim() != 2:
+            raise ValueError("A must be a 2-D tensor or a CsrMatrix")
+        if A.dtype not in (torch.float32, torch.float64):
+            raise ValueError(f"A must be float32 or float64, not {A.dtype}")
+        m, n = A.shape
+        if A.stride(1) != 1 or (m > 1 and A.stride(0) < n):
+            raise ValueError("A must be row-major with unit column stride")
+        tensors.append(A)
+        dtype = A.dtype
+    if b is not None:
+        if not isinstance(b, torch.Tensor) or b.dtype != dtype:
+            raise ValueError(f"b must be a tensor of A's dtype {dtype}")
+        if not b.is_contiguous() or b.numel() != m:
+            raise ValueError(f"b must be contiguous with m = {m} entries")
+        tensors.append(b)
+    if x is not None:
+        if not isinstance(x, torch.Tensor) or x.dtype != torch.float64:
+            raise ValueError("x must be a float64 tensor")
+        if not x.is_contiguous() or x.numel() != n:
+            raise ValueError(f"x must be contiguous with n = {n} entries")
+        tensors.append(x)
+    dev = tensors[0].device
+    for t in tensors:
+        if t.device != dev:
+            raise ValueError("A, b and x must be on the same device")
+    if need_cuda and dev.type != "cuda":
+        raise ValueError(f"A, b and x must be in GPU memory, not on {dev}")
+    return m, n
+
+
 def _describe(A) -> Matrix:
     if isinstance(A, CsrMatrix):
         return csr(A.row_ptr, A.col_idx, A.values, A.shape[0], A.shape[1])
@@ -46,6 +101,7 @@ def sketch(A, b=None, kind: str = "count", d: int = None, seed: int = 42, accum_
     """SA, Sb = S A, S b for a dense device tensor or a CsrMatrix A (and
     optional b)."""
     import torch
+    check_args(A, b)
     sk = sketch_desc(kind, d, seed, zeta)
     M = _describe(A)
     ws = _workspace(sns_sketch_workspace_size(sk, M), A.device)
@@ -64,6 +120,7 @@ def lstsq(A, b, kind: str = "count", d: int = None, seed: int = 42, refine=False
     """x (float64 device tensor) and Info for min ||A x - b||.  refine: False /
     "sas" (plain sketch-and-solve), True / "sap" (SAP-SAS) or "saa" (SAA-SAS)."""
     import torch
+    check_args(A, b)
     sk = sketch_desc(kind, d, seed, zeta)
     M = _describe(A)
     r = REFINE[refine]
@@ -83,6 +140,7 @@ def lstsq_batched(As, bs, ds, seeds, refine: bool = True, max_iters: int = 100, 
     import torch
     probs, xs = [], []
     for A, b, d, seed in zip(As, bs, ds, seeds):
+        check_args(A, b)
         x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
         o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0)
         sk = sketch_desc("sparse", d, seed, zeta) if zeta > 1 else sketch_desc("count", d, seed)
@@ -101,7 +159,9 @@ class Server:
     submit() queues a dense CountSketch (or, with zeta > 1, sparse sign
     embedding) problem (device tensors A, b; the
     answer goes to a new fp64 tensor) and returns a ticket; wait()/poll()
-    return (x, Info) once it has completed."""
+    return (x, Info) once it has completed.  submit() first waits for the
+    caller's current stream, so work queued there on A, b or x is complete
+    before the server's own streams touch them."""
 
     def __init__(self, pool_bytes: int, dtype=None, max_slots: int = 64,
                  queue_capacity: int = 65536, chunk_iters: int = 4, device=None):
@@ -114,10 +174,14 @@ class Server:
     def submit(self, A, b, d: int, seed: int, refine: bool = True, max_iters: int = 100,
                rtol: float = 1e-6, x=None, zeta: int = 1) -> int:
         import torch
+        check_args(A, b, x)
         if x is None:
             x = torch.empty(A.shape[1], dtype=torch.float64, device=A.device)
         o = opts(int(refine), max_iters if refine else 0, rtol if refine else 0.0)
         sk = sketch_desc("sparse", d, seed, zeta) if zeta > 1 else sketch_desc("count", d, seed)
+        # the server's streams do not wait on the caller's: whatever the
+        # caller's stream still has queued on A, b or x must finish first
+        torch.cuda.current_stream(A.device).synchronize()
         t = sns_serve_submit(self.handle, problem(sk, dense(A), b, x, o))
         self._live[t] = (A, b, x)  # keep the buffers alive while the request runs
         return t

@@ -182,8 +182,8 @@ def _dtype_code(t):
 
 def dense(A) -> Matrix:
     """Describe a 2-D device tensor (row-major, unit column stride) as sns_matrix."""
-    if A.dim() != 2 or A.stride(1) != 1:
-        raise ValueError("A must be 2-D with unit column stride")
+    if A.dim() != 2 or A.stride(1) != 1 or (A.shape[0] > 1 and A.stride(0) < A.shape[1]):
+        raise ValueError("A must be 2-D and row-major with unit column stride")
     return Matrix(A.shape[0], A.shape[1], _dtype_code(A), SNS_DENSE_ROWMAJOR, A.data_ptr(),
                   A.stride(0), None, None, 0)
 
