@@ -121,7 +121,8 @@ typedef struct {
   int max_iters;   /* LSQR iteration cap (refine = 1 or 2) */
   double rtol;     /* stop when ||Abar^T r|| / ||r|| <= rtol (1 - sqrt(n/d));
                       rtol = 0 runs exactly max_iters iterations */
-  int accum_fp64;  /* 1: accumulate the CountSketch in fp64 (fp32 inputs) */
+  int accum_fp64;  /* 1: accumulate the dense CountSketch in fp64 (fp32 inputs);
+                      the CSR sketch always accumulates in fp64 */
 } sns_solve_opts;
 
 typedef struct {

@@ -23,6 +23,9 @@ namespace sns {
 // Kernel timing hooks (no-ops unless timing is enabled).
 void timing_begin(const char* name, hipStream_t s);
 void timing_end(hipStream_t s);
+// The same for a phase of several launches (one region open per thread).
+void region_begin(const char* name, hipStream_t s);
+void region_end(hipStream_t s);
 
 #define SNS_LAUNCH(name, kernel, grid, block, lds, stream, ...)              \
   do {                                                                      \

@@ -485,6 +485,7 @@ QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
 
 sns_status launch_qr_job(const QrJob& j, hipStream_t st) {
   if (j.count == 0) return SNS_OK;
+  region_begin("qr", st);
   if (j.f64)
     SNS_LAUNCH("qr_load", k_qr_load<double>, dim3(grid_for(j.nload)), dim3(32, 8), 0, st, j.all,
                j.mload);
@@ -506,6 +507,7 @@ sns_status launch_qr_job(const QrJob& j, hipStream_t st) {
   const size_t lds = ((size_t)j.maxn + 4096 + 16) * sizeof(double);
   SNS_LAUNCH("qr_finish", k_qr_finish, dim3(grid_for((uint32_t)j.count)), dim3(1024), lds, st,
              j.all, j.mone);
+  region_end(st);
   SNS_HIP_TRY(hipGetLastError());
   return SNS_OK;
 }

@@ -5,7 +5,9 @@
 // sns_timing_enable(1) or by the environment variable SNS_TRACE=1, which also
 // prints the summary to stderr when the process exits.  Each bracketed launch
 // costs a few microseconds of device time for the two event records, so a
-// caller timing a whole solve selects only the kernels it reports.
+// caller timing a whole solve selects only the kernels it reports.  A region
+// (region_begin / region_end around a phase of several launches, e.g. the
+// whole QR) is timed the same way under its own name.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -44,6 +46,17 @@ Registry& reg() {
 
 thread_local Rec* t_open = nullptr;
 thread_local Rec t_pending;
+// a region (a phase of several launches) is timed in a slot of its own, so a
+// kernel inside it can be timed too
+thread_local Rec* t_region_open = nullptr;
+thread_local Rec t_region;
+
+bool selected(const Registry& r, const char* name) {
+  if (r.only.empty()) return true;
+  for (const std::string& k : r.only)
+    if (k == name) return true;
+  return false;
+}
 
 hipEvent_t take_event(Registry& r) {
   if (!r.pool.empty()) {
@@ -101,12 +114,7 @@ void timing_begin(const char* name, hipStream_t s) {
   Registry& r = reg();
   std::lock_guard<std::mutex> g(r.mu);
   check_env(r);
-  if (!r.on) return;
-  if (!r.only.empty()) {
-    bool hit = false;
-    for (const std::string& k : r.only) hit = hit || k == name;
-    if (!hit) return;
-  }
+  if (!r.on || !selected(r, name)) return;
   // launches being captured into a graph are not timed
   hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
@@ -125,6 +133,31 @@ void timing_end(hipStream_t s) {
   (void)hipEventRecord(t_open->b, s);
   r.recs.push_back(*t_open);
   t_open = nullptr;
+  if (r.recs.size() > 4096) collect(r);
+}
+
+void region_begin(const char* name, hipStream_t s) {
+  Registry& r = reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  check_env(r);
+  if (!r.on || !selected(r, name)) return;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
+  t_region.name = name;
+  t_region.a = take_event(r);
+  t_region.b = take_event(r);
+  if (!t_region.a || !t_region.b) return;
+  (void)hipEventRecord(t_region.a, s);
+  t_region_open = &t_region;
+}
+
+void region_end(hipStream_t s) {
+  if (!t_region_open) return;
+  Registry& r = reg();
+  std::lock_guard<std::mutex> g(r.mu);
+  (void)hipEventRecord(t_region_open->b, s);
+  r.recs.push_back(*t_region_open);
+  t_region_open = nullptr;
   if (r.recs.size() > 4096) collect(r);
 }
 

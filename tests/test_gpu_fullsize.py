@@ -137,19 +137,23 @@ def csr_problem(gpu_lib):
     return p, OSV.sketch_and_solve(p.A, p.b, "count", SEED, 4000).x
 
 
-@pytest.mark.parametrize("accum_fp64,tol", [(False, 1e-4), (True, 1e-5)])
-def test_csr_full_size_plain_solve(gpu_lib, csr_problem, accum_fp64, tol):
-    """Plain sketch-and-solve at full size.  kappa(SA) is about 4, so x0
-    moves by at most a few times the sketch's relative error: FP32 partial
-    sums (the benchmark's setting) or FP64 ones, SA rounded to FP32 either
-    way."""
+def test_csr_full_size_plain_solve(gpu_lib, csr_problem):
+    """Plain sketch-and-solve at full size, the benchmark's setting: the CSR
+    sketch accumulates in FP64 and rounds SA and Sb to FP32, then the FP64
+    QR.  kappa(SA) is about 4, so x0 moves by a few times FP32 rounding.
+    Every element of x0 is within 1e-5 of the oracle's, scaled by its largest
+    entry, and the accum_fp64 flag (meaningful for dense A only) changes no
+    bit."""
     import torch
     p, xr = csr_problem
     A = p.A
     M = gpu_lib.CsrMatrix(_dev(A.indptr.astype(np.int32), torch), _dev(A.indices.astype(np.int32), torch),
                           _dev(A.data, torch), A.shape)
-    x, info = gpu_lib.lstsq(M, _dev(p.b, torch), "count", 4000, SEED, accum_fp64=accum_fp64)
+    b = _dev(p.b, torch)
+    x, info = gpu_lib.lstsq(M, b, "count", 4000, SEED)
     assert info.status == 0
     xg = x.cpu().numpy()
-    err = np.linalg.norm(xg - xr) / np.linalg.norm(xr)
-    assert err <= tol, err
+    assert np.max(np.abs(xg - xr)) <= 1e-5 * np.max(np.abs(xr)), np.max(np.abs(xg - xr))
+    assert np.linalg.norm(xg - xr) <= 1e-5 * np.linalg.norm(xr)
+    x2, _ = gpu_lib.lstsq(M, b, "count", 4000, SEED, accum_fp64=True)
+    assert np.array_equal(x2.cpu().numpy(), xg)

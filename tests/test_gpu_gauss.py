@@ -94,3 +94,18 @@ def test_gaussian_plain_sketch_and_solve_parity(gpu_lib):
     r = OSV.sketch_and_solve(p.A, p.b, "gaussian", 42, 160)
     # fp32 sketch of a column-scaled A: x0 agrees to kappa(SA) * 1e-6 or so
     assert np.linalg.norm(x.cpu().numpy() - r.x) <= 1e-3 * np.linalg.norm(r.x)
+
+
+def test_gaussian_plain_solve_well_conditioned_parity(gpu_lib):
+    """N(0,1) FP32 A with d = 4n: x0 from the MFMA sketch within 1e-5 of the
+    oracle's sketch-and-solve on the same bf16 values, element by element
+    (scaled by max|x0|) and in norm."""
+    import torch
+    from workloads import dense_gaussian
+    p = dense_gaussian(30000, 40, seed=33, dtype=np.float32)
+    x, info = gpu_lib.lstsq(_dev(p.A, torch), _dev(p.b, torch), "gaussian", 160, 42)
+    assert info.status == 0
+    r = OSV.sketch_and_solve(p.A, p.b, "gaussian", 42, 160)
+    xg = x.cpu().numpy()
+    assert np.max(np.abs(xg - r.x)) <= 1e-5 * np.max(np.abs(r.x)), np.max(np.abs(xg - r.x))
+    assert np.linalg.norm(xg - r.x) <= 1e-5 * np.linalg.norm(r.x)

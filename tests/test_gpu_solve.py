@@ -36,6 +36,20 @@ def _qr_gpu(sns, torch, SA, Sb):
     return x0.cpu().numpy(), R.cpu().numpy(), info
 
 
+def _check_r_x0(R, Rr, x0, xr, tol=1e-12):
+    """Element by element: every entry of column j of R within tol times the
+    column's norm (Householder QR is backward stable column by column, and
+    ||R[:, j]|| = ||SA[:, j]||), every entry of x0 within tol times max|x0|
+    (times kappa(R) / 1e3 when R is worse conditioned than that); the
+    strictly lower part of R is exactly zero."""
+    cn = np.linalg.norm(Rr, axis=0)
+    assert np.all(np.abs(R - Rr) <= tol * cn[None, :]), np.max(np.abs(R - Rr) / cn[None, :])
+    assert np.all(np.tril(R, -1) == 0.0)
+    amp = max(1.0, np.linalg.cond(Rr) / 1e3)
+    assert np.max(np.abs(x0 - xr)) <= tol * amp * np.max(np.abs(xr)), np.max(np.abs(x0 - xr))
+    assert np.linalg.norm(x0 - xr) <= tol * amp * np.linalg.norm(xr)
+
+
 @pytest.mark.parametrize("d,n", [(200, 50), (1024, 256), (600, 600), (2100, 130), (80, 1),
                                  (513, 17), (4000, 97), (512, 16), (1025, 300), (4097, 40),
                                  (8192, 70), (257, 19), (4000, 1000), (8192, 600)])
@@ -48,8 +62,7 @@ def test_qr_solve_matches_oracle(gpu_lib, d, n):
     Rr, c, rho, _, _ = OQ.householder_qr_augmented(SA, Sb)
     xr = OQ.back_substitution(Rr, c)
     assert info.status == 0
-    assert np.linalg.norm(R - Rr) <= 1e-12 * np.linalg.norm(Rr)
-    assert np.linalg.norm(x0 - xr) <= 1e-12 * np.linalg.norm(xr) * max(1.0, np.linalg.cond(Rr) / 1e3)
+    _check_r_x0(R, Rr, x0, xr)
     assert abs(info.sketch_resid - rho) <= 1e-12 * max(rho, 1.0)
 
 
@@ -60,7 +73,7 @@ def test_qr_solve_fp32_input_and_rank_deficiency(gpu_lib):
     Sb = rng.standard_normal(300).astype(np.float32)
     x0, R, info = _qr_gpu(gpu_lib, torch, SA, Sb)
     Rr, c, rho, _, _ = OQ.householder_qr_augmented(SA.astype(np.float64), Sb.astype(np.float64))
-    assert np.linalg.norm(R - Rr) <= 1e-12 * np.linalg.norm(Rr)
+    _check_r_x0(R, Rr, x0, OQ.back_substitution(Rr, c))
     SA = rng.standard_normal((300, 40))
     SA[:, 7] = SA[:, 3]
     _, _, info = _qr_gpu(gpu_lib, torch, SA, rng.standard_normal(300))
@@ -76,6 +89,7 @@ def test_plain_fp64_20000x50(gpu_lib):
     r = OSV.sketch_and_solve(p.A, p.b, "count", 42, 200)
     xg = x.cpu().numpy()
     assert info.status == 0 and info.iters == 0
+    assert np.max(np.abs(xg - r.x)) <= 1e-12 * np.max(np.abs(r.x))
     assert np.linalg.norm(xg - r.x) <= 1e-12 * np.linalg.norm(r.x)
     assert abs(info.sketch_resid - r.rho) <= 1e-12 * r.rho
     # accuracy of the method itself (reported, not a parity bar)
@@ -175,3 +189,46 @@ def test_concurrent_solves_on_two_streams_from_one_thread(gpu_lib):
         assert info.status == 0 and info_s.status == 0
         assert info.iters == info_s.iters
         assert torch.equal(x, xs)
+
+
+# ------------------------------------------------------- failure statuses --
+# Numerical outcomes arrive in sns_info.status (SNS_ERR_NUMERICAL = 6,
+# SNS_ERR_NOT_CONVERGED = 5); every kernel runs its fixed trip counts on
+# non-finite data, so these cases end normally.
+
+@pytest.mark.parametrize("refine", [False, True])
+def test_nan_in_b_reports_numerical(gpu_lib, refine):
+    import torch
+    p = dense_gaussian(20000, 32, seed=41, dtype=np.float32)
+    b = p.b.copy()
+    b[1234] = np.nan
+    x, info = gpu_lib.lstsq(_dev(p.A, torch), _dev(b, torch), "count", 128, 42, refine=refine,
+                            max_iters=10, rtol=1e-6)
+    assert info.status == 6, info.status
+
+
+@pytest.mark.parametrize("refine", [False, True])
+def test_inf_in_a_reports_numerical(gpu_lib, refine):
+    import torch
+    p = dense_gaussian(20000, 32, seed=42, dtype=np.float64)
+    A = p.A.copy()
+    A[777, 5] = np.inf
+    x, info = gpu_lib.lstsq(_dev(A, torch), _dev(p.b, torch), "count", 128, 42, refine=refine,
+                            max_iters=10, rtol=1e-6)
+    assert info.status == 6, info.status
+
+
+def test_max_iters_before_stop_rule_reports_not_converged(gpu_lib):
+    """rtol = 1e-12 cannot be met in two iterations: status NOT_CONVERGED
+    with the iterate after max_iters returned, the same bits as a run of
+    exactly two iterations (rtol = 0)."""
+    import torch
+    p = dense_ill_conditioned(40000, 48, seed=43, cond=1e4, dtype=np.float32)
+    A, b = _dev(p.A, torch), _dev(p.b, torch)
+    x, info = gpu_lib.lstsq(A, b, "count", 192, 42, refine=True, max_iters=2, rtol=1e-12)
+    assert info.status == 5 and info.iters == 2, (info.status, info.iters)
+    x2, info2 = gpu_lib.lstsq(A, b, "count", 192, 42, refine=True, max_iters=2, rtol=0.0)
+    assert info2.status == 0 and info2.iters == 2
+    assert np.array_equal(x.cpu().numpy(), x2.cpu().numpy())
+    r = OSV.sap_sas(p.A, p.b, "count", 42, 192, 2)
+    assert np.linalg.norm(x.cpu().numpy() - r.x) <= 1e-5 * np.linalg.norm(r.x)
