@@ -147,7 +147,8 @@ def cpu_baseline(A, b, d, rtol, rows, full_m, kind, refine=1, zeta=1, rows_1core
     host = host_cpu()
     dt, iters = run(rows)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    out = {"value": full_m / rows / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
+    # one solve of the full m takes dt * full_m / rows seconds
+    out = {"value": rows / (full_m * dt), "unit": "solves/s", "cores": threads, "kind": "oracle",
            "sample": (f"first {rows} of {full_m} rows (n={A.shape[1]}, d={d}), one solve"
                       + (f" to rtol {rtol} ({iters} LSQR iterations)" if refine else "")
                       + f" in {dt:.2f}s with {threads} BLAS threads, time scaled by m"),
@@ -155,7 +156,7 @@ def cpu_baseline(A, b, d, rtol, rows, full_m, kind, refine=1, zeta=1, rows_1core
     r1 = min(rows_1core or rows, full_m)
     with threadpool_limits(limits=1):
         dt1, _ = run(r1)
-    out["single_core"] = {"value": full_m / r1 / dt1, "unit": "solves/s", "cores": 1,
+    out["single_core"] = {"value": r1 / (full_m * dt1), "unit": "solves/s", "cores": 1,
                           "sample": f"first {r1} rows, one solve in {dt1:.2f}s on one core, "
                                     f"time scaled by m", "seconds_sample": dt1}
     return out

@@ -185,6 +185,23 @@ sns_status sns_qr_solve(int64_t d, int64_t n, sns_dtype dtype, const void* SA, i
                         const void* Sb, double* x0, double* R, sns_info* info,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * QR solve as sns_qr_solve, same arguments and outputs, with the workspace in
+ * a static 64 MiB device array inside the library instead of caller memory.
+ * Each device the library runs on holds its own array until the process
+ * ends; its address is looked up on the first call on a device (with that
+ * device current).  No device or host memory is allocated by the call.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (two streams, or two host threads) race and give undefined
+ * results; serialise them.  Errors: as sns_qr_solve (argument checks first),
+ * and SNS_ERR_OUT_OF_MEMORY when the workspace sns_qr_solve_workspace_size
+ * reports for (d, n) exceeds 64 MiB (for example d = 4096 with n = 1000 fits,
+ * d = 8192 with n = 1000 does not); nothing is enqueued then. */
+sns_status sns_qr_solve_noalloc(int64_t d, int64_t n, sns_dtype dtype, const void* SA,
+                                int64_t ld_sa, const void* Sb, double* x0, double* R,
+                                sns_info* info, void* stream);
+
 /* Workspace bytes sns_lstsq needs. */
 sns_status sns_lstsq_workspace_size(const sns_sketch* sk, const sns_matrix* A,
                                     const sns_solve_opts* opts, size_t* bytes);

@@ -90,6 +90,9 @@ _SIGS = {
     "sns_qr_solve": (C.c_int, [C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int64, C.c_void_p,
                                C.c_void_p, C.c_void_p, C.POINTER(Info), C.c_void_p, C.c_size_t,
                                C.c_void_p]),
+    "sns_qr_solve_noalloc": (C.c_int, [C.c_int64, C.c_int64, C.c_int, C.c_void_p, C.c_int64,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Info),
+                                       C.c_void_p]),
     "sns_lstsq_workspace_size": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix),
                                            C.POINTER(SolveOpts), C.POINTER(C.c_size_t)]),
     "sns_lstsq": (C.c_int, [C.POINTER(Sketch), C.POINTER(Matrix), C.c_void_p, C.c_void_p,
@@ -255,6 +258,14 @@ def sns_qr_solve(d: int, n: int, SA, Sb, x0, R, workspace, info: Info | None = N
                                _ptr(R), C.byref(info) if info is not None else None,
                                _ptr(workspace), workspace.numel() * workspace.element_size(),
                                _stream(stream)), "sns_qr_solve")
+
+
+def sns_qr_solve_noalloc(d: int, n: int, SA, Sb, x0, R, info: Info | None = None, stream=None):
+    """sns_qr_solve with the workspace in the library's static device array."""
+    _check(load().sns_qr_solve_noalloc(d, n, _dtype_code(SA), _ptr(SA), SA.stride(0), _ptr(Sb),
+                                       _ptr(x0), _ptr(R),
+                                       C.byref(info) if info is not None else None,
+                                       _stream(stream)), "sns_qr_solve_noalloc")
 
 
 def sns_lstsq_workspace_size(sk: Sketch, A: Matrix, opt: SolveOpts) -> int:

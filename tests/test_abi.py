@@ -171,3 +171,21 @@ def test_tuning_table_round_trip(tmp_path):
     sns.sns_tune_clear()
     if os.path.exists(sns._binding.TUNING_PATH):
         sns.sns_tune_load(sns._binding.TUNING_PATH)
+
+
+def test_qr_solve_noalloc_host_checks():
+    """The allocation-free QR solve rejects bad arguments and sizes whose
+    workspace exceeds its 64 MiB static array before touching the device."""
+    import paper_2409_14309_amd as sns
+    lib = sns.load()
+    fake = 0x1000
+    f = lib.sns_qr_solve_noalloc
+    assert f(200, 50, 1, None, 50, fake, fake, None, None, None) == 1      # null SA
+    assert f(200, 50, 1, fake, 50, fake, None, None, None, None) == 1      # null x0
+    assert f(200, 50, 7, fake, 50, fake, fake, None, None, None) == 3      # bad dtype
+    assert f(40, 50, 1, fake, 50, fake, fake, None, None, None) == 2       # d < n
+    assert f(200, 50, 1, fake, 40, fake, fake, None, None, None) == 2      # ld < n
+    assert f(8192, 1000, 1, fake, 1000, fake, fake, None, None, None) == 7  # over 64 MiB
+    need = C.c_size_t()
+    assert lib.sns_qr_solve_workspace_size(4096, 1000, C.byref(need)) == 0
+    assert need.value <= 64 << 20  # the size the header promises fits
