@@ -195,6 +195,7 @@ __device__ __forceinline__ void sort_scatter_item(const SortArgs& a, uint32_t lo
   const BT* b = static_cast<const BT*>(a.b);
   BT* bperm = static_cast<BT*>(a.bperm);
   uint32_t nrow = rows && r0 + lane < r1 ? rows[r0 + lane] : 0u;
+  const int nbits = d > 1 ? 32 - __clz((int)(d - 1)) : 0;  // bits of the largest bucket
   for (int64_t r = r0; r < r1; r += 64) {
     const int64_t tk = r + lane;
     const bool valid = tk < r1;
@@ -208,18 +209,18 @@ __device__ __forceinline__ void sort_scatter_item(const SortArgs& a, uint32_t lo
     } else {
       hs = cs_hash(a.seed, d, (uint64_t)i);
     }
-    const uint32_t h = valid ? hs.h : 0xFFFFFFFFu;
-    // rank among the earlier lanes of this batch with the same bucket
-    uint32_t rank = 0;
-    bool last = true;
-#pragma unroll 8
-    for (int q = 0; q < 64; ++q) {
-      const uint32_t hq = __shfl(h, q, 64);
-      if (hq == h) {
-        if (q < lane) ++rank;
-        if (q > lane) last = false;
-      }
+    const uint32_t h = valid ? hs.h : 0u;
+    // lanes of this batch with the same bucket: the lanes holding a key whose
+    // bucket agrees with this lane's in every bit (one ballot per bit of d-1);
+    // the rank is the number of such lanes below this one
+    uint64_t peers = __ballot(valid);
+    for (int bit = 0; bit < nbits; ++bit) {
+      const bool on = (h >> bit) & 1u;
+      const uint64_t bal = __ballot(on);
+      peers &= on ? bal : ~bal;
     }
+    const uint32_t rank = (uint32_t)__popcll(peers & ((1ull << lane) - 1ull));
+    const bool last = lane == 63 || (peers >> (lane + 1)) == 0ull;
     if (valid) {
       const uint32_t pos = next[h] + rank;
       a.perm[pos] = (uint32_t)i | (hs.neg ? 0x80000000u : 0u);
