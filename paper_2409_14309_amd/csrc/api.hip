@@ -180,7 +180,9 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   Jobs J;
   build_lstsq_jobs(t, J, *sk, *A, b, x, o, w);
   if ((s = t.upload(st)) != SNS_OK) return s;
-  if (sk->kind == SNS_SKETCH_GAUSSIAN)
+  if (w.fused)
+    s = launch_fused_job(J.fused, st);
+  else if (sk->kind == SNS_SKETCH_GAUSSIAN)
     s = launch_gauss_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, w.gauss, st);
   else if (sk->kind == SNS_SKETCH_HADAMARD)
     s = launch_hadamard_sketch(*A, (uint32_t)sk->d, sk->seed, b, w.SA, w.Sb, w.gauss, st);
@@ -190,7 +192,7 @@ sns_status sns_lstsq(const sns_sketch* sk, const sns_matrix* A, const void* b, d
   else
     s = run_sketch_jobs(J, st);
   if (s != SNS_OK) return s;
-  if ((s = launch_qr_job(J.qr, st)) != SNS_OK) return s;
+  if (!w.fused && (s = launch_qr_job(J.qr, st)) != SNS_OK) return s;
   if (o.refine) {
     if ((s = run_lsqr_single(J.lsqr, o.max_iters, true, st)) != SNS_OK) return s;
   } else {
@@ -227,6 +229,7 @@ sns_status sns_lstsq_batched(const sns_problem* probs, int count, void* workspac
   Jobs J;
   build_batch_jobs(t, J, probs, count, B, true);
   if ((s = t.upload(st)) != SNS_OK) return s;
+  if ((s = launch_fused_job(J.fused, st)) != SNS_OK) return s;
   if ((s = run_sketch_jobs(J, st)) != SNS_OK) return s;
   if ((s = launch_qr_job(J.qr, st)) != SNS_OK) return s;
   int max_iters = 0;

@@ -262,6 +262,57 @@ struct QrJob {
 QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64);
 sns_status launch_qr_job(const QrJob& j, hipStream_t st);
 
+// ---------------------------------------------------------------- fused ----
+// Sketch, QR and x0 of problems with d <= 256 and n <= 64 (CountSketch,
+// dense) in one persistent launch over a device queue of row chunks
+// (fused.hip).  Writes what the blocked QR path writes for the refinement:
+// R (column-major), 1 / diag, x0, scal and the device sns_info.
+constexpr int64_t kMaxFusedRows = (int64_t(1) << 31) - 1;
+struct FusedCtl {
+  unsigned head;  // next queue item; zero in the uploaded table
+  unsigned pad[3];
+};
+struct FusedArgs {
+  const void* A;
+  const void* b;
+  int64_t ld, m;
+  int n, d;
+  uint64_t seed;
+  int64_t rc;          // rows per chunk
+  int nchunk, ngroup;  // chunks, and groups of chunks summed together
+  double* part;        // nchunk x d (n + 1) chunk partials (nchunk > 1)
+  double* gpart;       // ngroup x d (n + 1) group partials (ngroup > 1)
+  double* R;
+  double* invd;
+  double* x0;
+  double* scal;
+  sns_info* info;
+  unsigned cnt[12];    // [0] group arrivals, [1 + g] chunk arrivals of group g; zero in the table
+};
+struct FusedPlan {
+  int64_t rc = 0;
+  int nchunk = 0, ngroup = 0, dn = 0;
+};
+struct FusedJob {
+  bool f64 = false;
+  int count = 0;
+  const FusedCtl* ctl = nullptr;
+  const FusedArgs* args = nullptr;
+  Map map{};
+  uint32_t items = 0;
+};
+bool fused_eligible(const sns_sketch& sk, const sns_matrix& A);
+FusedPlan make_fused_plan(const sns_sketch& sk, const sns_matrix& A);
+void carve_fused(Carve& c, const FusedPlan& p, double*& part, double*& gpart);
+FusedArgs fused_args(const FusedPlan& p, const sns_sketch& sk, const sns_matrix& A, const void* b,
+                     double* part, double* gpart, const QrBufs& q, double* x0, sns_info* info);
+FusedJob build_fused_job(ArgTable& t, const std::vector<FusedArgs>& a, bool f64);
+sns_status launch_fused_job(const FusedJob& j, hipStream_t st);
+// The table image at host_src (pinned, *host_words 8-byte words) copied to
+// dev_dst by a kernel: a graph replays it with new contents each time.
+sns_status launch_fused_stage(const void* host_src, void* dev_dst, const uint64_t* host_words,
+                              hipStream_t st);
+
 // ----------------------------------------------------------------- LSQR ----
 struct LsqrState;  // device-resident scalars, defined in lsqr.hip
 struct LsqrBufs {

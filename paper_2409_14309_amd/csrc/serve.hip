@@ -162,24 +162,31 @@ void build_setup(ArgTable& t, sns::Jobs& J, const std::vector<Req*>& fresh, bool
   std::vector<sns::SortArgs> sa;
   std::vector<sns::GatherProb> ga;
   std::vector<sns::QrArgs> qa;
+  std::vector<sns::FusedArgs> fa;
   std::vector<sns::LsqrProb> la;
   for (Req* r : fresh) {
     const sns_problem& q = r->p;
     const sns::LstsqWs& w = r->w;
-    sa.push_back(sns::sort_args(w.sw.sp, q.sketch.seed, q.b, w.sw.sb));
-    sns::GatherProb g;
-    g.plan = w.sw.gp;
-    g.args = sns::gather_args(w.sw.gp, q.A, (uint32_t)q.sketch.d, w.sw.sb, true, w.SA, w.Sb,
-                              w.sw.part);
-    g.dtype = q.A.dtype;
-    ga.push_back(g);
-    qa.push_back(sns::qr_args(q.sketch.d, q.A.n, w.SA, q.A.n, w.Sb, w.q, w.q.xw, nullptr,
-                              r->info_dev));
+    if (w.fused) {
+      fa.push_back(sns::fused_args(w.fp, q.sketch, q.A, q.b, w.fpart, w.fgpart, w.q, w.q.xw,
+                                   r->info_dev));
+    } else {
+      sa.push_back(sns::sort_args(w.sw.sp, q.sketch.seed, q.b, w.sw.sb));
+      sns::GatherProb g;
+      g.plan = w.sw.gp;
+      g.args = sns::gather_args(w.sw.gp, q.A, (uint32_t)q.sketch.d, w.sw.sb, true, w.SA, w.Sb,
+                                w.sw.part);
+      g.dtype = q.A.dtype;
+      ga.push_back(g);
+      qa.push_back(sns::qr_args(q.sketch.d, q.A.n, w.SA, q.A.n, w.Sb, w.q, w.q.xw, nullptr,
+                                r->info_dev));
+    }
     if (q.opts.refine) la.push_back(r->lp);
   }
   J.sort = sns::build_sort_job(t, sa, f64);
   J.gather = sns::build_gather_job(t, ga);
   J.qr = sns::build_qr_job(t, qa, f64);
+  J.fused = sns::build_fused_job(t, fa, f64);
   J.lsqr = sns::build_lsqr_job(t, la, f64);
 }
 
@@ -255,6 +262,7 @@ sns_status sns_server::round(std::vector<Req*>& fresh, std::vector<Req*>& pendin
     build_setup(t, J, fresh, f64);
     if (t.bytes() > tab_bytes) return SNS_ERR_OUT_OF_MEMORY;
     if ((s = t.upload(s2)) != SNS_OK) return s;
+    if ((s = sns::launch_fused_job(J.fused, s2)) != SNS_OK) return s;
     if ((s = sns::run_sketch_jobs(J, s2)) != SNS_OK) return s;
     if ((s = sns::launch_qr_job(J.qr, s2)) != SNS_OK) return s;
     if ((s = sns::launch_lsqr_setup(J.lsqr, s2)) != SNS_OK) return s;

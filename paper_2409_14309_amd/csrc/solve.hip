@@ -84,6 +84,10 @@ void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
   } else if (A.layout == SNS_CSR) {
     w.csr_bytes = csr_workspace_bytes(A, (uint32_t)sk.d, o.accum_fp64 != 0);
     w.csr = c.take<char>(w.csr_bytes);
+  } else if (fused_eligible(sk, A)) {
+    w.fused = true;
+    w.fp = make_fused_plan(sk, A);
+    carve_fused(c, w.fp, w.fpart, w.fgpart);
   } else {
     carve_sketch(c, sk, A, true, o.accum_fp64 != 0, w.sw);
   }
@@ -103,12 +107,18 @@ void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
 
 void build_lstsq_jobs(ArgTable& t, Jobs& J, const sns_sketch& sk, const sns_matrix& A,
                       const void* b, double* x, const sns_solve_opts& o, const LstsqWs& w) {
-  if ((sk.kind == SNS_SKETCH_COUNT || sk.kind == SNS_SKETCH_SPARSE_SIGN) &&
-      A.layout == SNS_DENSE_ROWMAJOR)
-    add_sketch_jobs(t, J, sk, A, b, w.SA, w.Sb, w.sw);
-  const std::vector<QrArgs> qa{
-      qr_args(sk.d, A.n, w.SA, A.n, w.Sb, w.q, w.q.xw, nullptr, w.info)};
-  J.qr = build_qr_job(t, qa, A.dtype == SNS_F64);
+  if (w.fused) {
+    J.fused = build_fused_job(
+        t, std::vector<FusedArgs>{fused_args(w.fp, sk, A, b, w.fpart, w.fgpart, w.q, w.q.xw, w.info)},
+        A.dtype == SNS_F64);
+  } else {
+    if ((sk.kind == SNS_SKETCH_COUNT || sk.kind == SNS_SKETCH_SPARSE_SIGN) &&
+        A.layout == SNS_DENSE_ROWMAJOR)
+      add_sketch_jobs(t, J, sk, A, b, w.SA, w.Sb, w.sw);
+    const std::vector<QrArgs> qa{
+        qr_args(sk.d, A.n, w.SA, A.n, w.Sb, w.q, w.q.xw, nullptr, w.info)};
+    J.qr = build_qr_job(t, qa, A.dtype == SNS_F64);
+  }
   if (o.refine) {
     LsqrProb lp;
     lp.plan = w.lp;
@@ -166,18 +176,24 @@ void build_batch_jobs(ArgTable& t, Jobs& J, const sns_problem* P, int count, con
   std::vector<SortArgs> sa;
   std::vector<GatherProb> ga;
   std::vector<QrArgs> qa;
+  std::vector<FusedArgs> fa;
   std::vector<LsqrProb> la;
   for (int i = 0; i < count; ++i) {
     const sns_problem& q = P[i];
     const LstsqWs& w = B.w[i];
     const void* b = real ? q.b : nullptr;
-    sa.push_back(sort_args(w.sw.sp, q.sketch.seed, b, w.sw.sb));
-    GatherProb g;
-    g.plan = w.sw.gp;
-    g.args = gather_args(w.sw.gp, q.A, (uint32_t)q.sketch.d, w.sw.sb, true, w.SA, w.Sb, w.sw.part);
-    g.dtype = q.A.dtype;
-    ga.push_back(g);
-    qa.push_back(qr_args(q.sketch.d, q.A.n, w.SA, q.A.n, w.Sb, w.q, w.q.xw, nullptr, B.infos + i));
+    if (w.fused) {
+      fa.push_back(fused_args(w.fp, q.sketch, q.A, b, w.fpart, w.fgpart, w.q, w.q.xw, B.infos + i));
+    } else {
+      sa.push_back(sort_args(w.sw.sp, q.sketch.seed, b, w.sw.sb));
+      GatherProb g;
+      g.plan = w.sw.gp;
+      g.args =
+          gather_args(w.sw.gp, q.A, (uint32_t)q.sketch.d, w.sw.sb, true, w.SA, w.Sb, w.sw.part);
+      g.dtype = q.A.dtype;
+      ga.push_back(g);
+      qa.push_back(qr_args(q.sketch.d, q.A.n, w.SA, q.A.n, w.Sb, w.q, w.q.xw, nullptr, B.infos + i));
+    }
     if (q.opts.refine) {
       LsqrProb lp;
       lp.plan = w.lp;
@@ -190,6 +206,7 @@ void build_batch_jobs(ArgTable& t, Jobs& J, const sns_problem* P, int count, con
   J.sort = build_sort_job(t, sa, f64);
   J.gather = build_gather_job(t, ga);
   J.qr = build_qr_job(t, qa, f64);
+  J.fused = build_fused_job(t, fa, f64);
   J.lsqr = build_lsqr_job(t, la, f64);
 }
 

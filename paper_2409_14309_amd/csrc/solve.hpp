@@ -38,6 +38,7 @@ struct Jobs {
   SortJob sort;
   std::vector<GatherLaunch> gather;
   QrJob qr;
+  FusedJob fused;  // sketch + QR of the small problems, one persistent launch
   LsqrJob lsqr;
 };
 
@@ -56,6 +57,10 @@ size_t table_bytes(F&& build) {
 }
 
 struct LstsqWs {
+  bool fused = false;  // sketch and QR in the persistent fused launch
+  FusedPlan fp;
+  double* fpart = nullptr;
+  double* fgpart = nullptr;
   SketchWs sw;
   void* gauss = nullptr;  // Gaussian sketch partials or the Hadamard sketch's blocks
   void* csr = nullptr;    // CSR sketch workspace
