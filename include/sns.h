@@ -266,6 +266,22 @@ sns_status sns_lstsq_batched_workspace_size(const sns_problem* probs, int count,
 sns_status sns_lstsq_batched(const sns_problem* probs, int count, void* workspace,
                              size_t ws_bytes, sns_info* infos, int use_graph, void* stream);
 
+/* The set-up of a small problem (CountSketch, dense A, d <= 256, n <= 64,
+ * m (n + 1) <= 2^21):
+ * sketch of [A | b] (Sec. 1.2 steps 1-2), Householder QR of [SA | Sb] and
+ * x0 = R^{-1} c (step 3), runs in one persistent launch shared by every such
+ * problem of a sns_lstsq call, a batch or a server round: a fixed grid claims
+ * row chunks of all of them from a device queue, and the work-group that
+ * completes a problem's sketch factors it in registers.  Larger problems take
+ * the blocked path (bucket sort, gather, panel QR).  The fused form is off by
+ * default (on one MI355X the blocked path sets these problems up faster);
+ * sns_fused_enable(1) turns it on for every later call and server set-up,
+ * sns_fused_enable(0) back off.  Results of the two forms differ in rounding,
+ * and so do workspace sizes: query them after switching.  The switch is
+ * process-wide and must not change while calls or servers are in flight. */
+void sns_fused_enable(int on);
+int sns_fused_enabled(void);
+
 /* ------------------------------------------------------------- serving --
  * A server solves submitted problems with continuous batching.  A scheduler
  * thread owns two HIP streams and works in rounds: it admits waiting requests

@@ -17,6 +17,7 @@ from ._binding import (SNS_CSR, SNS_DENSE_ROWMAJOR, SNS_F32, SNS_F64, SNS_SKETCH
                        sns_lstsq_batched_workspace_size, sns_lstsq_workspace_size,
                        sns_qr_solve, sns_qr_solve_noalloc, sns_qr_solve_workspace_size, sns_sketch_apply,
                        sns_sketch_workspace_size, sns_status_string, sns_timing_enable,
+                       sns_fused_enable, sns_fused_enabled,
                        sns_timing_reset, sns_timing_select, sns_timing_summary, sns_version)
 
 

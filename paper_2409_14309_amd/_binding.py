@@ -116,6 +116,8 @@ _SIGS = {
     "sns_tune_load": (C.c_int, [C.c_char_p]),
     "sns_tune_save": (C.c_int, [C.c_char_p]),
     "sns_timing_enable": (None, [C.c_int]),
+    "sns_fused_enable": (None, [C.c_int]),
+    "sns_fused_enabled": (C.c_int, []),
     "sns_timing_select": (None, [C.c_char_p]),
     "sns_timing_reset": (None, []),
     "sns_timing_summary": (C.c_int, [C.c_char_p, C.c_size_t]),
@@ -378,6 +380,19 @@ def sns_tune_load(path: str):
 
 def sns_tune_save(path: str):
     _check(load().sns_tune_save(path.encode()), "sns_tune_save")
+
+
+# ----------------------------------------------------- fused set-up ----
+
+def sns_fused_enable(on: bool = True):
+    """Small problems (d <= 256, n <= 64, m (n + 1) <= 2^21) set up in the
+    persistent fused launch, or (False, the default) on the blocked path like
+    larger ones."""
+    load().sns_fused_enable(1 if on else 0)
+
+
+def sns_fused_enabled() -> bool:
+    return bool(load().sns_fused_enabled())
 
 
 # ------------------------------------------------------------- timing ----

@@ -263,14 +263,15 @@ QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64);
 sns_status launch_qr_job(const QrJob& j, hipStream_t st);
 
 // ---------------------------------------------------------------- fused ----
-// Sketch, QR and x0 of problems with d <= 256 and n <= 64 (CountSketch,
-// dense) in one persistent launch over a device queue of row chunks
+// Sketch, QR and x0 of problems with d <= 256, n <= 64 and m (n + 1) <= 2^21
+// (CountSketch, dense) in one persistent launch over a device queue of row chunks
 // (fused.hip).  Writes what the blocked QR path writes for the refinement:
 // R (column-major), 1 / diag, x0, scal and the device sns_info.
-constexpr int64_t kMaxFusedRows = (int64_t(1) << 31) - 1;
+constexpr int64_t kMaxFusedElems = int64_t(1) << 21;  // m (n + 1) of a fused problem
 struct FusedCtl {
   unsigned head;  // next queue item; zero in the uploaded table
-  unsigned pad[3];
+  int nprob;      // problems in the table
+  unsigned pad[2];
 };
 struct FusedArgs {
   const void* A;
@@ -278,10 +279,12 @@ struct FusedArgs {
   int64_t ld, m;
   int n, d;
   uint64_t seed;
+  int vec;             // rows of A may be read four entries at a time (16-byte aligned)
   int64_t rc;          // rows per chunk
   int nchunk, ngroup;  // chunks, and groups of chunks summed together
   double* part;        // nchunk x d (n + 1) chunk partials (nchunk > 1)
   double* gpart;       // ngroup x d (n + 1) group partials (ngroup > 1)
+  double* msys;        // d x (n + 1): the summed system, handed to the QR's registers
   double* R;
   double* invd;
   double* x0;
@@ -303,15 +306,33 @@ struct FusedJob {
 };
 bool fused_eligible(const sns_sketch& sk, const sns_matrix& A);
 FusedPlan make_fused_plan(const sns_sketch& sk, const sns_matrix& A);
-void carve_fused(Carve& c, const FusedPlan& p, double*& part, double*& gpart);
+struct FusedBufs {
+  double* part = nullptr;
+  double* gpart = nullptr;
+  double* msys = nullptr;
+};
+void carve_fused(Carve& c, const FusedPlan& p, FusedBufs& f);
 FusedArgs fused_args(const FusedPlan& p, const sns_sketch& sk, const sns_matrix& A, const void* b,
-                     double* part, double* gpart, const QrBufs& q, double* x0, sns_info* info);
+                     const FusedBufs& f, const QrBufs& q, double* x0, sns_info* info);
 FusedJob build_fused_job(ArgTable& t, const std::vector<FusedArgs>& a, bool f64);
 sns_status launch_fused_job(const FusedJob& j, hipStream_t st);
-// The table image at host_src (pinned, *host_words 8-byte words) copied to
-// dev_dst by a kernel: a graph replays it with new contents each time.
-sns_status launch_fused_stage(const void* host_src, void* dev_dst, const uint64_t* host_words,
-                              hipStream_t st);
+// A fused table of fixed capacity for replayed graphs: control block, then
+// max_probs FusedArgs, then max_probs + 1 chunk offsets.
+struct FusedTableLayout {
+  int max_probs = 0;
+  size_t args_off = 0, off_off = 0, bytes = 0;
+};
+FusedTableLayout fused_table_layout(int max_probs);
+// Writes the table image of the problems a into img (host memory) and its
+// size in 8-byte words; false if they exceed the capacity.
+bool fused_table_fill(void* img, const FusedTableLayout& L, const std::vector<FusedArgs>& a,
+                      uint64_t* words);
+// Captures (on st) and instantiates the graph of one set-up: a kernel copies
+// the image at host_img (pinned; *host_words words, read at replay time)
+// into dev_tab, then the persistent fused launch runs on dev_tab's problems.
+sns_status fused_graph_create(void* dev_tab, const FusedTableLayout& L, const void* host_img,
+                              const uint64_t* host_words, bool f64, hipStream_t st,
+                              hipGraphExec_t* exec);
 
 // ----------------------------------------------------------------- LSQR ----
 struct LsqrState;  // device-resident scalars, defined in lsqr.hip

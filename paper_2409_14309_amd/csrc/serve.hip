@@ -4,12 +4,17 @@
 //   1. admit waiting requests in arrival order while a slot is free and the
 //      request's workspace fits in the pool (first-fit allocator over the
 //      caller's device memory);
-//   2. set the admitted requests up in one batched launch per kernel
-//      (CountSketch sort and gather, QR, and for refined requests X = R^{-1}
-//      and the LSQR state) on a second stream, so that the set-up (mostly the
-//      QR: one work-group per request and panel step) overlaps the iterations
-//      of step 3; the requests join the batch in the next round, once the
-//      iteration stream has waited for their set-up;
+//   2. set the admitted requests up on a second stream, so that the set-up
+//      overlaps the iterations of step 3: the small ones (d <= 256, n <= 64,
+//      m (n + 1) <= 2^21)
+//      in the persistent fused sketch + QR launch, replayed from a captured
+//      HIP graph whose first kernel copies this round's problem table from
+//      pinned memory (two graphs, tables and images used in turn, each
+//      rewritten only after its previous replay has finished); the others in
+//      one batched launch per kernel (CountSketch sort and gather, blocked
+//      QR); then, for refined requests, X = R^{-1} and the LSQR state.  The
+//      requests join the batch in the next round, once the iteration stream
+//      has waited for their set-up;
 //   3. advance every refining request by `chunk_iters` LSQR iterations, again
 //      one batched launch per kernel over all of them, and read back which
 //      ones have stopped;
@@ -126,6 +131,15 @@ struct sns_server {
   char* tab_fin = nullptr;
   size_t tab_bytes = 0;
   int* flags_dev = nullptr;
+  // set-up of the small requests: the fused sketch + QR launch replayed from
+  // one of two graphs, each with its own device table and pinned image
+  sns::FusedTableLayout ftl;
+  char* ftab[2] = {nullptr, nullptr};
+  void* fimg[2] = {nullptr, nullptr};
+  uint64_t* fwords[2] = {nullptr, nullptr};
+  hipGraphExec_t fexec[2] = {nullptr, nullptr};
+  hipEvent_t fev[2] = {nullptr, nullptr};
+  int fbuf = 0;
   // pinned host mirrors
   int* flags_host = nullptr;
   sns_info* infos_host = nullptr;
@@ -152,23 +166,26 @@ struct sns_server {
   void run();
   sns_status round(std::vector<Req*>& fresh, std::vector<Req*>& pending,
                    std::vector<Req*>& refining);
+  sns_status init_fused();
+  void release_fused();
   void complete(std::vector<Req*>& fin, sns_status err);
 };
 
 namespace {
 
 // One round's jobs for the freshly admitted requests.
-void build_setup(ArgTable& t, sns::Jobs& J, const std::vector<Req*>& fresh, bool f64) {
+void build_setup(ArgTable& t, sns::Jobs& J, const std::vector<Req*>& fresh, bool f64,
+                 std::vector<sns::FusedArgs>& fa) {
   std::vector<sns::SortArgs> sa;
   std::vector<sns::GatherProb> ga;
   std::vector<sns::QrArgs> qa;
-  std::vector<sns::FusedArgs> fa;
   std::vector<sns::LsqrProb> la;
+  fa.clear();
   for (Req* r : fresh) {
     const sns_problem& q = r->p;
     const sns::LstsqWs& w = r->w;
     if (w.fused) {
-      fa.push_back(sns::fused_args(w.fp, q.sketch, q.A, q.b, w.fpart, w.fgpart, w.q, w.q.xw,
+      fa.push_back(sns::fused_args(w.fp, q.sketch, q.A, q.b, w.fb, w.q, w.q.xw,
                                    r->info_dev));
     } else {
       sa.push_back(sns::sort_args(w.sw.sp, q.sketch.seed, q.b, w.sw.sb));
@@ -186,7 +203,6 @@ void build_setup(ArgTable& t, sns::Jobs& J, const std::vector<Req*>& fresh, bool
   J.sort = sns::build_sort_job(t, sa, f64);
   J.gather = sns::build_gather_job(t, ga);
   J.qr = sns::build_qr_job(t, qa, f64);
-  J.fused = sns::build_fused_job(t, fa, f64);
   J.lsqr = sns::build_lsqr_job(t, la, f64);
 }
 
@@ -233,6 +249,33 @@ void sns_server::complete(std::vector<Req*>& fin, sns_status err) {
   cv_work.notify_all();
 }
 
+// Pinned images, events and the two set-up graphs of the fused launch.
+sns_status sns_server::init_fused() {
+  for (int i = 0; i < 2; ++i) {
+    SNS_HIP_TRY(hipHostMalloc(&fimg[i], ftl.bytes, hipHostMallocDefault));
+    SNS_HIP_TRY(hipHostMalloc((void**)&fwords[i], sizeof(uint64_t), hipHostMallocDefault));
+    *fwords[i] = 0;
+    SNS_HIP_TRY(hipEventCreateWithFlags(&fev[i], hipEventDisableTiming));
+    sns_status s = sns::fused_graph_create(ftab[i], ftl, fimg[i], fwords[i],
+                                           cfg.dtype == SNS_F64, stream2, &fexec[i]);
+    if (s != SNS_OK) return s;
+  }
+  return SNS_OK;
+}
+
+void sns_server::release_fused() {
+  for (int i = 0; i < 2; ++i) {
+    if (fexec[i]) (void)hipGraphExecDestroy(fexec[i]);
+    if (fev[i]) (void)hipEventDestroy(fev[i]);
+    if (fimg[i]) (void)hipHostFree(fimg[i]);
+    if (fwords[i]) (void)hipHostFree(fwords[i]);
+    fexec[i] = nullptr;
+    fev[i] = nullptr;
+    fimg[i] = nullptr;
+    fwords[i] = nullptr;
+  }
+}
+
 sns_status sns_server::round(std::vector<Req*>& fresh, std::vector<Req*>& pending,
                              std::vector<Req*>& refining) {
   const bool f64 = cfg.dtype == SNS_F64;
@@ -259,10 +302,21 @@ sns_status sns_server::round(std::vector<Req*>& fresh, std::vector<Req*>& pendin
     hipStream_t s2 = stream2;
     ArgTable t(tab_setup);
     sns::Jobs J;
-    build_setup(t, J, fresh, f64);
+    std::vector<sns::FusedArgs> fa;
+    build_setup(t, J, fresh, f64, fa);
     if (t.bytes() > tab_bytes) return SNS_ERR_OUT_OF_MEMORY;
+    if (!fa.empty()) {
+      // the image of this buffer is free once its previous replay has run
+      const int bi = fbuf;
+      fbuf ^= 1;
+      SNS_HIP_TRY(hipEventSynchronize(fev[bi]));
+      if (!sns::fused_table_fill(fimg[bi], ftl, fa, fwords[bi])) return SNS_ERR_OUT_OF_MEMORY;
+      sns::region_begin("fused", s2);
+      SNS_HIP_TRY(hipGraphLaunch(fexec[bi], s2));
+      sns::region_end(s2);
+      SNS_HIP_TRY(hipEventRecord(fev[bi], s2));
+    }
     if ((s = t.upload(s2)) != SNS_OK) return s;
-    if ((s = sns::launch_fused_job(J.fused, s2)) != SNS_OK) return s;
     if ((s = sns::run_sketch_jobs(J, s2)) != SNS_OK) return s;
     if ((s = sns::launch_qr_job(J.qr, s2)) != SNS_OK) return s;
     if ((s = sns::launch_lsqr_setup(J.lsqr, s2)) != SNS_OK) return s;
@@ -386,6 +440,8 @@ sns_status sns_serve_create(const sns_serve_config* cfg, sns_server** out) {
   s->tab_iter = c.take<char>(s->tab_bytes);
   s->tab_fin = c.take<char>(s->tab_bytes);
   s->flags_dev = c.take<int>((size_t)cfg->max_slots);
+  s->ftl = sns::fused_table_layout(cfg->max_slots);
+  for (int i = 0; i < 2; ++i) s->ftab[i] = c.take<char>(s->ftl.bytes);
   c.off = sns::align_up(c.off);
   if (!c.ok() || c.off >= cfg->pool_bytes) {
     delete s;
@@ -405,10 +461,22 @@ sns_status sns_serve_create(const sns_serve_config* cfg, sns_server** out) {
       hipHostMalloc((void**)&s->infos_host, sizeof(sns_info) * cfg->max_slots,
                     hipHostMallocDefault) != hipSuccess) {
     if (s->flags_host) (void)hipHostFree(s->flags_host);
+    if (s->infos_host) (void)hipHostFree(s->infos_host);
     if (s->ev_setup) (void)hipEventDestroy(s->ev_setup);
     if (s->ev) (void)hipEventDestroy(s->ev);
     if (s->stream2) (void)hipStreamDestroy(s->stream2);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return SNS_ERR_HIP;
+  }
+  if (s->init_fused() != SNS_OK) {
+    s->release_fused();
+    (void)hipHostFree(s->flags_host);
+    (void)hipHostFree(s->infos_host);
+    (void)hipEventDestroy(s->ev_setup);
+    (void)hipEventDestroy(s->ev);
+    (void)hipStreamDestroy(s->stream2);
+    (void)hipStreamDestroy(s->stream);
     delete s;
     return SNS_ERR_HIP;
   }
@@ -505,6 +573,7 @@ sns_status sns_serve_destroy(sns_server* srv) {
   srv->reqs.clear();
   (void)hipStreamSynchronize(srv->stream2);
   (void)hipStreamSynchronize(srv->stream);
+  srv->release_fused();
   (void)hipHostFree(srv->flags_host);
   (void)hipHostFree(srv->infos_host);
   (void)hipEventDestroy(srv->ev_setup);

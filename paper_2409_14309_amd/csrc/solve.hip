@@ -87,7 +87,7 @@ void carve_lstsq_bufs(Carve& c, const sns_sketch& sk, const sns_matrix& A,
   } else if (fused_eligible(sk, A)) {
     w.fused = true;
     w.fp = make_fused_plan(sk, A);
-    carve_fused(c, w.fp, w.fpart, w.fgpart);
+    carve_fused(c, w.fp, w.fb);
   } else {
     carve_sketch(c, sk, A, true, o.accum_fp64 != 0, w.sw);
   }
@@ -109,7 +109,7 @@ void build_lstsq_jobs(ArgTable& t, Jobs& J, const sns_sketch& sk, const sns_matr
                       const void* b, double* x, const sns_solve_opts& o, const LstsqWs& w) {
   if (w.fused) {
     J.fused = build_fused_job(
-        t, std::vector<FusedArgs>{fused_args(w.fp, sk, A, b, w.fpart, w.fgpart, w.q, w.q.xw, w.info)},
+        t, std::vector<FusedArgs>{fused_args(w.fp, sk, A, b, w.fb, w.q, w.q.xw, w.info)},
         A.dtype == SNS_F64);
   } else {
     if ((sk.kind == SNS_SKETCH_COUNT || sk.kind == SNS_SKETCH_SPARSE_SIGN) &&
@@ -183,7 +183,7 @@ void build_batch_jobs(ArgTable& t, Jobs& J, const sns_problem* P, int count, con
     const LstsqWs& w = B.w[i];
     const void* b = real ? q.b : nullptr;
     if (w.fused) {
-      fa.push_back(fused_args(w.fp, q.sketch, q.A, b, w.fpart, w.fgpart, w.q, w.q.xw, B.infos + i));
+      fa.push_back(fused_args(w.fp, q.sketch, q.A, b, w.fb, w.q, w.q.xw, B.infos + i));
     } else {
       sa.push_back(sort_args(w.sw.sp, q.sketch.seed, b, w.sw.sb));
       GatherProb g;

@@ -59,8 +59,7 @@ size_t table_bytes(F&& build) {
 struct LstsqWs {
   bool fused = false;  // sketch and QR in the persistent fused launch
   FusedPlan fp;
-  double* fpart = nullptr;
-  double* fgpart = nullptr;
+  FusedBufs fb;
   SketchWs sw;
   void* gauss = nullptr;  // Gaussian sketch partials or the Hadamard sketch's blocks
   void* csr = nullptr;    // CSR sketch workspace

@@ -148,16 +148,27 @@ def sparse_csr(m: int, n: int, seed: int, nnz_per_col: int = 1000, dense_block: 
 
 
 def serving_requests(count: int, rate: float, seed: int, log2_m=(12.0, 20.0),
-                     n_choices=(16, 32, 64, 128, 256), d_factor: int = 4):
+                     n_choices=(16, 32, 64, 128, 256), d_factor: int = 4,
+                     pool_rows: int = 1 << 23):
     """Poisson arrivals at `rate` per second; m = floor(2^U[lo, hi]); n uniform
-    over n_choices; d = d_factor * n.  Returns a list of dicts sorted by arrival."""
+    over n_choices; d = d_factor * n.  Returns a list of dicts sorted by arrival.
+    "offset" is the request's first row in the pool of its n: the requests of
+    one n take consecutive windows through a pool of pool_rows rows (wrapping
+    round), so requests that are in flight together never share rows."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / rate, size=count))
     ms = np.floor(2.0 ** rng.uniform(log2_m[0], log2_m[1], size=count)).astype(np.int64)
     ns = rng.choice(np.asarray(n_choices), size=count)
     seeds = rng.integers(0, 2**31 - 1, size=count)
-    return [{"id": i, "t": float(t[i]), "m": int(ms[i]), "n": int(ns[i]), "d": int(d_factor * ns[i]),
-             "seed": int(seeds[i])} for i in range(count)]
+    nxt = {int(n): 0 for n in n_choices}
+    out = []
+    for i in range(count):
+        n, m = int(ns[i]), int(ms[i])
+        off = nxt[n] if nxt[n] + m <= pool_rows else 0
+        nxt[n] = off + m
+        out.append({"id": i, "t": float(t[i]), "m": m, "n": n, "d": int(d_factor * n),
+                    "seed": int(seeds[i]), "offset": off})
+    return out
 
 
 def serving_pool(rows: int = 1 << 20, n_choices=(16, 32, 64, 128, 256), seed: int = 0,
@@ -184,7 +195,11 @@ def serving_pool(rows: int = 1 << 20, n_choices=(16, 32, 64, 128, 256), seed: in
 
 
 def request_window(req: dict, rows: int):
-    """First row of the request's window in its pool (deterministic)."""
+    """First row of the request's window in its pool (deterministic): the
+    consecutive-window offset when the request carries one and it fits."""
+    off = req.get("offset")
+    if off is not None and off + int(req["m"]) <= rows:
+        return int(off)
     return int(req["seed"]) % (rows - int(req["m"]) + 1)
 
 
