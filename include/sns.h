@@ -369,10 +369,62 @@ sns_status sns_tune_workspace_size(const sns_matrix* A, size_t* bytes);
  * (m_lo = m_hi = A->m).  Synchronous. */
 sns_status sns_tune_pass(const sns_matrix* A, int reps, void* workspace, size_t ws_bytes,
                          sns_tune_entry* best, void* stream);
-/* The table: add or replace the entry with the same dtype, n, m_lo, m_hi;
- * clear; load (appends; text lines "dtype n m_lo m_hi lpr nch grid unroll us",
- * '#' comments) and save.  Thread-safe. */
+/* The CountSketch gather (dense A, Sec. 1.2 step 1) has two launch-shape
+ * parameters: lanes per row (4..64, a power of two; one row-slot of that many
+ * lanes streams a tile of lpr x 16 bytes of each row) and segments per bucket
+ * (1..64, a power of two; each segment keeps at least 256 rows, and more than
+ * one segment adds a fixed-order reduction of the partial sketches).  An
+ * entry matches a problem by dtype, n, d and an m range.  The blocked QR
+ * (Sec. 1.2 step 3) has a panel configuration (0..4: rows per thread, panel
+ * width and threads of the panel work-group, holding d <= 512, 1024, 2048,
+ * 4096 and 8192 rows) and trailing columns per work-group (1 or 2); an entry
+ * matches by d range and n range.  Both change the order of the sums, so a
+ * result is reproducible for a given table. */
+typedef struct {
+  int dtype;             /* sns_dtype */
+  int n, d;
+  int64_t m_lo, m_hi;    /* rows covered, inclusive */
+  int lpr, nseg;
+  double us;             /* measured time of one gather (informational) */
+} sns_tune_gather_entry;
+
+typedef struct {
+  int d_lo, d_hi;        /* sketch rows covered, inclusive */
+  int n_lo, n_hi;        /* columns covered, inclusive */
+  int cfg, cb;
+  double us;             /* measured time of one factorisation (informational) */
+} sns_tune_qr_entry;
+
+/* Workspace for sns_tune_gather on A with d buckets (dense A, n <= d <= m,
+ * d <= 16384, n <= 4096). */
+sns_status sns_tune_gather_workspace_size(const sns_matrix* A, int64_t d, size_t* bytes);
+/* Bucket-sort A's rows once (seed as in sns_sketch; b: m device values of
+ * A's dtype), then time every candidate gather shape (`reps` timed launches
+ * each after one warm-up; candidates whose column tile is more than twice n
+ * are skipped) and write the fastest to *best (m_lo = m_hi = A->m).
+ * Synchronous. */
+sns_status sns_tune_gather(const sns_matrix* A, const void* b, int64_t d, uint64_t seed, int reps,
+                           void* workspace, size_t ws_bytes, sns_tune_gather_entry* best,
+                           void* stream);
+/* Workspace for sns_tune_qr of a d x n sketch (1 <= n <= d <= 8192, n <= 4096). */
+sns_status sns_tune_qr_workspace_size(int64_t d, int64_t n, size_t* bytes);
+/* Time the blocked QR and solve of [SA | Sb] (device, row-major SA d x n with
+ * leading dimension n, Sb d; dtype SNS_F32 or SNS_F64) under every panel
+ * configuration that holds d and both trailing widths, and write the fastest
+ * to *best (d_lo = d_hi = d, n_lo = n_hi = n).  Synchronous. */
+sns_status sns_tune_qr(int dtype, int64_t d, int64_t n, const void* SA, const void* Sb, int reps,
+                       void* workspace, size_t ws_bytes, sns_tune_qr_entry* best, void* stream);
+
+/* The table: add or replace the entry with the same key (pass: dtype, n,
+ * m_lo, m_hi; gather: dtype, n, d, m_lo, m_hi; QR: d and n ranges; lookups
+ * take the first entry that covers a problem); clear (all three kinds);
+ * load (appends; text lines "dtype n m_lo m_hi lpr nch grid unroll us" for
+ * the pass, "G dtype n d m_lo m_hi lpr nseg us" for the gather,
+ * "Q d_lo d_hi n_lo n_hi cfg cb us" for the QR, '#' comments; a malformed
+ * line loads nothing from the file) and save.  Thread-safe. */
 sns_status sns_tune_set(const sns_tune_entry* e);
+sns_status sns_tune_gather_set(const sns_tune_gather_entry* e);
+sns_status sns_tune_qr_set(const sns_tune_qr_entry* e);
 sns_status sns_tune_clear(void);
 sns_status sns_tune_load(const char* path);
 sns_status sns_tune_save(const char* path);

@@ -9,7 +9,9 @@ from __future__ import annotations
 from ._binding import (SNS_CSR, SNS_DENSE_ROWMAJOR, SNS_F32, SNS_F64, SNS_SKETCH_COUNT,  # noqa: F401
                        ServeConfig, ServeStats, TuneEntry, sns_serve_create, sns_serve_destroy,
                        sns_tune_clear, sns_tune_load, sns_tune_pass, sns_tune_save, sns_tune_set,
-                       sns_tune_workspace_size,
+                       sns_tune_workspace_size, TuneGatherEntry, TuneQrEntry, sns_tune_gather,
+                       sns_tune_gather_set, sns_tune_gather_workspace_size, sns_tune_qr,
+                       sns_tune_qr_set, sns_tune_qr_workspace_size,
                        sns_serve_poll, sns_serve_stats_get, sns_serve_submit, sns_serve_wait,
                        SNS_SKETCH_GAUSSIAN, Info, Matrix, Problem, Sketch, SnsError, SolveOpts,
                        csr, dense, exported_symbols, load, opts, problem, sketch_desc,

@@ -71,6 +71,16 @@ class TuneEntry(C.Structure):
                 ("us", C.c_double)]
 
 
+class TuneGatherEntry(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("n", C.c_int), ("d", C.c_int), ("m_lo", C.c_int64),
+                ("m_hi", C.c_int64), ("lpr", C.c_int), ("nseg", C.c_int), ("us", C.c_double)]
+
+
+class TuneQrEntry(C.Structure):
+    _fields_ = [("d_lo", C.c_int), ("d_hi", C.c_int), ("n_lo", C.c_int), ("n_hi", C.c_int),
+                ("cfg", C.c_int), ("cb", C.c_int), ("us", C.c_double)]
+
+
 TUNING_PATH = os.path.join(HERE, "tuning.txt")
 
 _lib = None
@@ -112,6 +122,16 @@ _SIGS = {
     "sns_tune_pass": (C.c_int, [C.POINTER(Matrix), C.c_int, C.c_void_p, C.c_size_t,
                                 C.POINTER(TuneEntry), C.c_void_p]),
     "sns_tune_set": (C.c_int, [C.POINTER(TuneEntry)]),
+    "sns_tune_gather_workspace_size": (C.c_int, [C.POINTER(Matrix), C.c_int64,
+                                                 C.POINTER(C.c_size_t)]),
+    "sns_tune_gather": (C.c_int, [C.POINTER(Matrix), C.c_void_p, C.c_int64, C.c_uint64, C.c_int,
+                                  C.c_void_p, C.c_size_t, C.POINTER(TuneGatherEntry),
+                                  C.c_void_p]),
+    "sns_tune_qr_workspace_size": (C.c_int, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
+    "sns_tune_qr": (C.c_int, [C.c_int, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int,
+                              C.c_void_p, C.c_size_t, C.POINTER(TuneQrEntry), C.c_void_p]),
+    "sns_tune_gather_set": (C.c_int, [C.POINTER(TuneGatherEntry)]),
+    "sns_tune_qr_set": (C.c_int, [C.POINTER(TuneQrEntry)]),
     "sns_tune_clear": (C.c_int, []),
     "sns_tune_load": (C.c_int, [C.c_char_p]),
     "sns_tune_save": (C.c_int, [C.c_char_p]),
@@ -368,6 +388,46 @@ def sns_tune_pass(A: Matrix, reps: int, workspace, stream=None) -> TuneEntry:
 
 def sns_tune_set(e: TuneEntry):
     _check(load().sns_tune_set(C.byref(e)), "sns_tune_set")
+
+
+def sns_tune_gather_workspace_size(A: Matrix, d: int) -> int:
+    n = C.c_size_t(0)
+    _check(load().sns_tune_gather_workspace_size(C.byref(A), d, C.byref(n)),
+           "sns_tune_gather_workspace_size")
+    return n.value
+
+
+def sns_tune_gather(A: Matrix, b, d: int, seed: int, reps: int, workspace,
+                    stream=None) -> TuneGatherEntry:
+    e = TuneGatherEntry()
+    _check(load().sns_tune_gather(C.byref(A), _ptr(b), d, seed, reps, _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), C.byref(e),
+                                  _stream(stream)), "sns_tune_gather")
+    return e
+
+
+def sns_tune_qr_workspace_size(d: int, n: int) -> int:
+    k = C.c_size_t(0)
+    _check(load().sns_tune_qr_workspace_size(d, n, C.byref(k)), "sns_tune_qr_workspace_size")
+    return k.value
+
+
+def sns_tune_qr(SA, Sb, reps: int, workspace, stream=None) -> TuneQrEntry:
+    """SA: (d, n) contiguous device tensor, Sb: (d,), both float32 or float64."""
+    d, n = SA.shape
+    e = TuneQrEntry()
+    _check(load().sns_tune_qr(_dtype_code(SA), d, n, _ptr(SA), _ptr(Sb), reps, _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), C.byref(e),
+                              _stream(stream)), "sns_tune_qr")
+    return e
+
+
+def sns_tune_gather_set(e: TuneGatherEntry):
+    _check(load().sns_tune_gather_set(C.byref(e)), "sns_tune_gather_set")
+
+
+def sns_tune_qr_set(e: TuneQrEntry):
+    _check(load().sns_tune_qr_set(C.byref(e)), "sns_tune_qr_set")
 
 
 def sns_tune_clear():

@@ -1,10 +1,16 @@
-"""Autotuner driver for the refinement pass's launch shape.
+"""Autotuner driver for the launch shapes of the refinement pass, the
+CountSketch gather and the blocked QR.
 
-For each (dtype, n, m) of the sweep it fills a device matrix with N(0,1)
+For each (dtype, n, m) of the pass sweep it fills a device matrix with N(0,1)
 values, asks the library to time every candidate plan of the fused LSQR pass
 (sns_tune_pass) and records the fastest as a tuning-table entry covering the
 m range around the swept m (geometric midpoints between neighbours).  The
-table is written where the Python binding loads it from.
+gather sweep does the same for the CountSketch gather with d = 4n
+(sns_tune_gather: lanes per row, segments per bucket).  The QR sweep times
+the panel configurations and trailing widths on a Gaussian [SA | Sb] of each
+listed (d, n) (sns_tune_qr) and records an entry for exactly that shape;
+other shapes keep the built-in rule.  The table is written where the Python
+binding loads it from.
 
     python -m paper_2409_14309_amd.autotune [--out PATH] [--quick]
     python -m paper_2409_14309_amd.autotune --merge --f64-n 1000   # add shapes to the table
@@ -20,6 +26,14 @@ F32_N = (16, 32, 64, 128, 256, 512, 1024, 2048)
 F64_N = (16, 32, 50, 64, 128, 256, 512)
 MS = (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22)
 MAX_BYTES = 16 << 30
+# gather sweep (d = 4n): the serving mix's widths in FP32, and FP64 widths
+G_F32_N = (16, 32, 64, 128, 256)
+G_F64_N = (16, 32, 50, 64, 128, 256)
+G_MS = (1 << 12, 1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22)
+# QR sweep: (d, n) of the serving mix (d = 4n), the 20000 x 50 problem, the
+# dense 256-column and 512-column problems and the 1000-column sparse one
+QR_SHAPES = ((64, 16), (128, 32), (256, 64), (512, 128), (1024, 256), (200, 50), (2048, 512),
+             (4000, 1000))
 
 
 def sweep(dtype_code: int, ns, ms, reps: int, log):
@@ -46,6 +60,53 @@ def sweep(dtype_code: int, ns, ms, reps: int, log):
     return out
 
 
+def _m_range(ms, k):
+    lo = 1 if k == 0 else int(math.sqrt(ms[k - 1] * ms[k]))
+    hi = (1 << 31) - 1 if k == len(ms) - 1 else int(math.sqrt(ms[k] * ms[k + 1])) - 1
+    return lo, hi
+
+
+def sweep_gather(dtype_code: int, ns, ms, reps: int, log):
+    import torch
+
+    import paper_2409_14309_amd as sns
+    tdt = torch.float64 if dtype_code == sns.SNS_F64 else torch.float32
+    es = 8 if dtype_code == sns.SNS_F64 else 4
+    out = []
+    for n in ns:
+        d = 4 * n
+        ms_n = [m for m in ms if m * n * es <= MAX_BYTES and m >= d]
+        for k, m in enumerate(ms_n):
+            A = torch.randn(m, n, dtype=tdt, device="cuda")
+            b = torch.randn(m, dtype=tdt, device="cuda")
+            M = sns.dense(A)
+            ws = torch.empty(sns.sns_tune_gather_workspace_size(M, d), dtype=torch.uint8,
+                             device="cuda")
+            e = sns.sns_tune_gather(M, b, d, 1234 + k, reps, ws)
+            e.m_lo, e.m_hi = _m_range(ms_n, k)
+            out.append(e)
+            log(f"gather dtype {dtype_code} n {n:4d} d {d:5d} m {m:8d}: lpr {e.lpr:2d} "
+                f"nseg {e.nseg:2d}  {e.us:9.2f} us")
+            del A, b, ws
+    return out
+
+
+def sweep_qr(shapes, reps: int, log):
+    import torch
+
+    import paper_2409_14309_amd as sns
+    out = []
+    for d, n in shapes:
+        g = torch.Generator(device="cuda").manual_seed(d * 131 + n)
+        SA = torch.randn(d, n, dtype=torch.float32, device="cuda", generator=g)
+        Sb = torch.randn(d, dtype=torch.float32, device="cuda", generator=g)
+        ws = torch.empty(sns.sns_tune_qr_workspace_size(d, n), dtype=torch.uint8, device="cuda")
+        e = sns.sns_tune_qr(SA, Sb, reps, ws)
+        out.append(e)
+        log(f"qr d {d:5d} n {n:5d}: cfg {e.cfg} cb {e.cb}  {e.us:9.2f} us")
+    return out
+
+
 def main(argv=None):
     import paper_2409_14309_amd as sns
     ap = argparse.ArgumentParser()
@@ -56,7 +117,10 @@ def main(argv=None):
                     help="keep the current table and add or replace only the swept shapes")
     ap.add_argument("--f32-n", type=int, nargs="*", default=None, help="fp32 widths to sweep")
     ap.add_argument("--f64-n", type=int, nargs="*", default=None, help="fp64 widths to sweep")
+    ap.add_argument("--only", choices=("pass", "gather", "qr"), nargs="*", default=None,
+                    help="sweep only these kinds (default: all three)")
     args = ap.parse_args(argv)
+    kinds = set(args.only or ("pass", "gather", "qr"))
 
     def log(msg):
         print(f"[autotune] {msg}", file=sys.stderr, flush=True)
@@ -70,11 +134,27 @@ def main(argv=None):
     f32_n, f64_n, ms = (F32_N, F64_N, MS) if not args.quick else ((64,), (50,), (1 << 14, 1 << 18))
     if args.f32_n is not None or args.f64_n is not None:
         f32_n, f64_n = tuple(args.f32_n or ()), tuple(args.f64_n or ())
-    entries = sweep(sns.SNS_F32, f32_n, ms, args.reps, log) + sweep(sns.SNS_F64, f64_n, ms, args.reps, log)
-    for e in entries:
-        sns.sns_tune_set(e)
+    count = 0
+    if "pass" in kinds:
+        entries = (sweep(sns.SNS_F32, f32_n, ms, args.reps, log)
+                   + sweep(sns.SNS_F64, f64_n, ms, args.reps, log))
+        for e in entries:
+            sns.sns_tune_set(e)
+        count += len(entries)
+    if "gather" in kinds:
+        gf32, gf64, gms = (G_F32_N, G_F64_N, G_MS) if not args.quick else ((64,), (50,), (1 << 16,))
+        entries = (sweep_gather(sns.SNS_F32, gf32, gms, args.reps, log)
+                   + sweep_gather(sns.SNS_F64, gf64, gms, args.reps, log))
+        for e in entries:
+            sns.sns_tune_gather_set(e)
+        count += len(entries)
+    if "qr" in kinds:
+        entries = sweep_qr(QR_SHAPES if not args.quick else ((256, 64),), args.reps, log)
+        for e in entries:
+            sns.sns_tune_qr_set(e)
+        count += len(entries)
     sns.sns_tune_save(out)
-    log(f"{len(entries)} entries in {time.time() - t0:.1f}s -> {out}")
+    log(f"{count} entries in {time.time() - t0:.1f}s -> {out}")
 
 
 if __name__ == "__main__":

@@ -175,28 +175,43 @@ void dispatch_lpr(const GatherLaunch& g, hipStream_t st) {
 
 }  // namespace
 
-GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64, int64_t keys) {
+GatherPlan gather_plan_with(const sns_matrix& A, uint32_t d, bool acc64, int64_t keys, int lpr,
+                            int nseg) {
   GatherPlan g;
   const size_t es = A.dtype == SNS_F64 ? 8 : 4;
   const int vmax = (int)(16 / es);
   const bool aligned = ((uintptr_t)A.values % 16 == 0) && (A.ld % vmax == 0);
   g.vec = aligned ? vmax : 1;
-  const int64_t lanes = (A.n + g.vec - 1) / g.vec;
-  int lpr = 4;
-  while (lpr < 64 && lpr < lanes) lpr <<= 1;
-  g.lpr = lpr;
-  g.ct = lpr * g.vec;
+  g.lpr = lpr < 4 ? 4 : (lpr > 64 ? 64 : lpr);
+  g.ct = g.lpr * g.vec;
   g.coltiles = (int)((A.n + g.ct - 1) / g.ct);
   g.acc64 = acc64 || A.dtype == SNS_F64;
-  // enough work-groups to fill the device, each segment keeping >= 256 rows
-  const int64_t wgs = (int64_t)d * g.coltiles;
-  int64_t nseg = (1024 + wgs - 1) / wgs;
   const int64_t maxseg = (keys >= 0 ? keys : A.m) / ((int64_t)d * 256);
-  if (nseg > maxseg) nseg = maxseg;
-  if (nseg < 1) nseg = 1;
-  if (nseg > 64) nseg = 64;
-  g.nseg = (int)nseg;
+  int64_t ns = nseg;
+  if (ns > maxseg) ns = maxseg;
+  if (ns < 1) ns = 1;
+  if (ns > 64) ns = 64;
+  g.nseg = (int)ns;
   return g;
+}
+
+GatherPlan make_gather_plan(const sns_matrix& A, uint32_t d, bool acc64, int64_t keys) {
+  const size_t es = A.dtype == SNS_F64 ? 8 : 4;
+  const int vmax = (int)(16 / es);
+  const bool aligned = ((uintptr_t)A.values % 16 == 0) && (A.ld % vmax == 0);
+  const int vec = aligned ? vmax : 1;
+  int tl = 0, ts = 0;
+  if (tune_gather_lookup(A.dtype, A.n, d, keys >= 0 ? keys : A.m, &tl, &ts))
+    return gather_plan_with(A, d, acc64, keys, tl, ts);
+  // built-in rule: the fewest lanes per row that cover n in one column tile,
+  // and enough work-groups to fill the device, each segment keeping >= 256 rows
+  const int64_t lanes = (A.n + vec - 1) / vec;
+  int lpr = 4;
+  while (lpr < 64 && lpr < lanes) lpr <<= 1;
+  const int64_t coltiles = (A.n + (int64_t)lpr * vec - 1) / ((int64_t)lpr * vec);
+  const int64_t wgs = (int64_t)d * coltiles;
+  int64_t nseg = (1024 + wgs - 1) / wgs;
+  return gather_plan_with(A, d, acc64, keys, lpr, (int)(nseg > 64 ? 64 : nseg));
 }
 
 size_t gather_partial_bytes(const GatherPlan& g, const sns_matrix& A, uint32_t d) {

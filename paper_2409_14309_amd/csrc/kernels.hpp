@@ -357,6 +357,20 @@ struct LsqrPlan {
 LsqrPlan make_lsqr_plan(const sns_matrix& A);
 // Tuning-table lookup (tune.hip): the entry for (dtype, n, m), if any.
 bool tune_lookup(sns_dtype dt, int64_t n, int64_t m, LsqrPlan* p);
+// Tuned gather shape (lanes per row, segments per bucket) and blocked-QR
+// shape (panel configuration, trailing columns per work-group), if the table
+// has an entry for the problem.
+bool tune_gather_lookup(sns_dtype dt, int64_t n, int64_t d, int64_t m, int* lpr, int* nseg);
+bool tune_qr_lookup(int64_t d, int64_t n, int* cfg, int* cb);
+// Gather plan with the given lanes per row and segments (clamped to what the
+// problem allows).
+GatherPlan gather_plan_with(const sns_matrix& A, uint32_t d, bool acc64, int64_t keys, int lpr,
+                            int nseg);
+// Rows a QR panel configuration holds (d <= capacity), or 0 if cfg is unknown.
+int64_t qr_cfg_capacity(int cfg);
+// The QR job with every problem forced to one panel configuration and
+// trailing-column count (for the tuner).
+QrJob build_qr_job_forced(ArgTable& t, const std::vector<QrArgs>& a, bool f64, int cfg, int cb);
 // Whether the pass is instantiated for (lpr, nch).
 bool lsqr_plan_valid(int lpr, int nch);
 // Time the fused pass on A with plan p: average microseconds over `reps`

@@ -372,12 +372,26 @@ __global__ __launch_bounds__(1024) void k_qr_finish(const QrArgs* __restrict__ P
   qr_finish_item(P[map_find(mp, it)], sh);
 }
 
-int qr_cfg(int64_t d) {
+int qr_cfg_builtin(int64_t d) {
   if (d <= 512) return 0;
   if (d <= 1024) return 1;
   if (d <= 2048) return 2;
   if (d <= 4096) return 3;
   return 4;
+}
+
+// Panel configuration and trailing columns of a problem: a tuning-table
+// entry when one covers (d, n) and its configuration holds d, else the
+// built-in rule.
+void qr_shape(int64_t d, int64_t n, int* cfg, int* cb) {
+  int c = 0, b = 0;
+  if (tune_qr_lookup(d, n, &c, &b) && qr_cfg_capacity(c) >= d && (b == 1 || b == 2)) {
+    *cfg = c;
+    *cb = b;
+    return;
+  }
+  *cfg = qr_cfg_builtin(d);
+  *cb = trail_cb(n);
 }
 
 template <int MAXR, int NB, int NT, int CB>
@@ -440,17 +454,27 @@ QrArgs qr_args(int64_t d, int64_t n, const void* SA, int64_t ld_sa, const void* 
   return a;
 }
 
-QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
+namespace {
+
+// force_cfg < 0: each problem's own shape (qr_shape); else every problem in
+// configuration force_cfg with force_cb trailing columns per work-group.
+QrJob build_qr_job_impl(ArgTable& t, const std::vector<QrArgs>& a, bool f64, int force_cfg,
+                        int force_cb) {
   QrJob j;
   j.f64 = f64;
   j.count = (int)a.size();
   if (a.empty()) return j;
   std::vector<uint32_t> load, one, ext;
+  std::vector<int> pcfg, pcb;
   for (const QrArgs& x : a) {
     load.push_back((uint32_t)(((x.d + 31) / 32) * ((x.n + 1 + 31) / 32)));
     ext.push_back((uint32_t)(((x.n + 31) / 32) * ((x.n + 31) / 32)));
     one.push_back(1u);
     j.maxn = x.n > j.maxn ? x.n : j.maxn;
+    int c = force_cfg, b = force_cb;
+    if (force_cfg < 0) qr_shape(x.d, x.n, &c, &b);
+    pcfg.push_back(c);
+    pcb.push_back(b);
   }
   j.all = t.add(a.data(), a.size());
   j.mload = t.map(load, &j.nload);
@@ -462,8 +486,9 @@ QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
     std::vector<QrArgs> sub;
     std::vector<uint32_t> cone, ctr;
     int64_t maxn = 0;
-    for (const QrArgs& x : a) {
-      if (qr_cfg(x.d) != cfg || trail_cb(x.n) != cb) continue;
+    for (size_t k = 0; k < a.size(); ++k) {
+      const QrArgs& x = a[k];
+      if (pcfg[k] != cfg || pcb[k] != cb) continue;
       sub.push_back(x);
       cone.push_back(1u);
       ctr.push_back((uint32_t)((x.n + cb - 1) / cb));
@@ -481,6 +506,27 @@ QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
     j.cls.push_back(c);
   }
   return j;
+}
+
+}  // namespace
+
+QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
+  return build_qr_job_impl(t, a, f64, -1, 0);
+}
+
+QrJob build_qr_job_forced(ArgTable& t, const std::vector<QrArgs>& a, bool f64, int cfg, int cb) {
+  return build_qr_job_impl(t, a, f64, cfg, cb);
+}
+
+int64_t qr_cfg_capacity(int cfg) {
+  switch (cfg) {
+    case 0: return 2 * 256;
+    case 1: return 4 * 256;
+    case 2: return 4 * 512;
+    case 3: return 8 * 512;
+    case 4: return 16 * 512;
+    default: return 0;
+  }
 }
 
 sns_status launch_qr_job(const QrJob& j, hipStream_t st) {

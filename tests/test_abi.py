@@ -148,6 +148,10 @@ def test_tuning_table_round_trip(tmp_path):
     sns.sns_tune_set(a)
     sns.sns_tune_set(b)
     sns.sns_tune_set(sns.TuneEntry(0, 256, 1, 1 << 20, 32, 4, 1024, 2, 99.0))  # replaces a
+    sns.sns_tune_gather_set(sns.TuneGatherEntry(0, 50, 200, 1, 1 << 22, 8, 4, 60.5))
+    sns.sns_tune_gather_set(sns.TuneGatherEntry(0, 50, 200, 1, 1 << 22, 16, 2, 55.0))  # replaces
+    sns.sns_tune_qr_set(sns.TuneQrEntry(1, 512, 1, 128, 0, 1, 300.25))
+    sns.sns_tune_qr_set(sns.TuneQrEntry(513, 1024, 1, 256, 2, 2, 800.0))
     p1 = tmp_path / "t1.txt"
     sns.sns_tune_save(str(p1))
     sns.sns_tune_clear()
@@ -157,14 +161,29 @@ def test_tuning_table_round_trip(tmp_path):
     assert p1.read_text() == p2.read_text()
     rows = [ln.split() for ln in p1.read_text().splitlines() if not ln.startswith("#")]
     assert rows == [["0", "256", "1", "1048576", "32", "4", "1024", "2", "99.000"],
-                    ["1", "50", "4096", "65535", "16", "1", "64", "2", "7.250"]]
+                    ["1", "50", "4096", "65535", "16", "1", "64", "2", "7.250"],
+                    ["G", "0", "50", "200", "1", "4194304", "16", "2", "55.000"],
+                    ["Q", "1", "512", "1", "128", "0", "1", "300.250"],
+                    ["Q", "513", "1024", "1", "256", "2", "2", "800.000"]]
     import pytest
     with pytest.raises(sns.SnsError):
         sns.sns_tune_set(sns.TuneEntry(0, 64, 1, 10, 8, 2, 64, 1, 0.0))  # (8, 2) not a pass shape
-    bad = tmp_path / "bad.txt"
-    bad.write_text("0 64 1 10 16 4 64 1 1.0\n0 64 oops\n")
-    with pytest.raises(sns.SnsError):
-        sns.sns_tune_load(str(bad))
+    with pytest.raises(sns.SnsError):  # 24 lanes per row: not a power of two
+        sns.sns_tune_gather_set(sns.TuneGatherEntry(0, 50, 200, 1, 10, 24, 1, 0.0))
+    with pytest.raises(sns.SnsError):  # 128 segments
+        sns.sns_tune_gather_set(sns.TuneGatherEntry(0, 50, 200, 1, 10, 16, 128, 0.0))
+    with pytest.raises(sns.SnsError):  # configuration 0 holds at most 512 rows
+        sns.sns_tune_qr_set(sns.TuneQrEntry(1, 600, 1, 128, 0, 1, 0.0))
+    with pytest.raises(sns.SnsError):  # three trailing columns
+        sns.sns_tune_qr_set(sns.TuneQrEntry(1, 500, 1, 128, 0, 3, 0.0))
+    for text in ("0 64 1 10 16 4 64 1 1.0\n0 64 oops\n",
+                 "G 0 50 200 1 10 16 2 1.0\nG 0 50 200 1 10 12 2 1.0\n",
+                 "Q 1 512 1 128 0 1 1.0\nQ 1 9000 1 128 4 1 1.0\n",
+                 "Q 1 512 1 128\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text(text)
+        with pytest.raises(sns.SnsError):
+            sns.sns_tune_load(str(bad))
     p3 = tmp_path / "t3.txt"
     sns.sns_tune_save(str(p3))
     assert p3.read_text() == p1.read_text()
