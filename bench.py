@@ -78,7 +78,7 @@ def kernel_source_hash(*names) -> str:
 
 # kernels whose launch times the solve bench reports
 REPORTED_KERNELS = ("lsqr_pass", "cs_gather", "sort_count", "scan_segments", "scan_buckets",
-                    "sort_scatter", "gauss_mfma", "form_y", "srht_pass1", "srht_pass", "srht_sample",
+                    "sort_place", "sort_scatter", "gauss_mfma", "form_y", "srht_pass1", "srht_pass", "srht_sample",
                     # phases of several launches, each timed as one region
                     "qr", "csr_sketch")
 
@@ -705,7 +705,7 @@ def main():
     qr = roofline("qr") if "qr" in kt else None
     csr_rec = roofline("csr_sketch") if "csr_sketch" in kt else None
     cs = kt.get("cs_gather")
-    sort_us = sum(kt[k][2] for k in ("sort_count", "scan_segments", "scan_buckets", "sort_scatter")
+    sort_us = sum(kt[k][2] for k in ("sort_count", "scan_segments", "scan_buckets", "sort_place", "sort_scatter")
                   if k in kt)
     countsketch = None
     if cs:

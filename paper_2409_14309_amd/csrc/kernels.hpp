@@ -71,6 +71,14 @@ __device__ __forceinline__ int map_find(const Map& mp, uint32_t item) {
   return lo;
 }
 
+// Work-groups are handed to the 8 XCDs in turn.  Item order that gives XCD x
+// the x-th contiguous eighth of the first 8 floor(n / 8) items (the rest keep
+// their place), so neighbouring items share one L2.  A bijection on [0, n).
+__device__ __forceinline__ uint32_t xcd_order(uint32_t h, uint32_t n) {
+  const uint32_t q = n / 8u;
+  return h < 8u * q ? (h % 8u) * q + h / 8u : h;
+}
+
 // Work-groups to launch for `total` items: one per item (work-groups past
 // the last item return at once, so a launch may be sized for more).
 inline unsigned grid_for(uint32_t total) { return total ? total : 1u; }
@@ -106,6 +114,8 @@ constexpr size_t kArgTableAlign = 16;
 // Stable counting sort of rows 0..m-1 by CountSketch bucket.  Produces
 // perm[m] (row id with the sign in bit 31, rows ascending inside a bucket),
 // bucket_ptr[d+1], and, when b is given, bperm[m] = s(i) b[i] in perm order.
+// The counting pass keeps each key's bucket and sign (hkey, 2 bytes a key)
+// for the placing pass, so every key is hashed once.
 struct SortPlan {
   int64_t m = 0;        // keys: rows x zeta
   uint32_t d = 0;
@@ -121,6 +131,7 @@ inline uint32_t sketch_zeta(const sns_sketch& sk) {
   return sk.kind == SNS_SKETCH_SPARSE_SIGN ? (uint32_t)sk.zeta : 1u;
 }
 struct SortBufs {
+  uint16_t* hkey;  // bucket of each key (bits 0-14) and its sign (bit 15)
   uint32_t* perm;
   void* bperm;
   uint32_t* bucket_ptr;
@@ -139,6 +150,7 @@ struct SortArgs {
   const uint32_t* rows;
   const uint32_t* mdev;
   const void* b;
+  uint16_t* hkey;
   uint32_t* perm;
   void* bperm;
   uint32_t* bucket_ptr;
@@ -154,6 +166,9 @@ struct SortJob {
   uint32_t ncount = 0, nseg = 0, nscan = 0;
   uint32_t maxd = 1;
   bool f64 = false;
+  bool staged = false;   // place through LDS (every group's keys fit)
+  int cap = 0;           // staged keys per group
+  size_t place_lds = 0;  // LDS bytes of the staged placing
   int count = 0;
 };
 SortJob build_sort_job(ArgTable& t, const std::vector<SortArgs>& a, bool f64);
