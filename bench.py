@@ -49,10 +49,10 @@ WORKLOADS = {
                                  "synthetic (seeded; A = G diag(sigma) V^T, kappa 1e6)"),
     "gauss_bf16_262144x512": ("dense_scaled_columns", 262144, 512, 2048, "gaussian",
                               "synthetic (seeded; N(0,1) columns scaled 1 .. 1e-3)"),
-    # Sec. 3.1 benchmark family: kappa 1e10, beta 1e-10, n = 1000, m up to 1e6, fp64
     "csr_fp32_16777216x1000": ("sparse_csr", 1 << 24, 1000, 4000, "count",
                                "synthetic (seeded; 1000 uniform rows per column with N(0,1) values "
                                "plus a dense N(0,1) 1000 x 1000 block, b = A x + 1e-3 N(0,1))"),
+    # Sec. 3.1 benchmark family: kappa 1e10, beta 1e-10, n = 1000, m up to 1e6, fp64
     "paper_fp64_1000000x1000": ("paper_benchmark_device", 1000000, 1000, 4000, "count",
                                 "synthetic (seeded on the device; A = U diag(sigma) V^T with "
                                 "Haar U, V, sigma log-spaced 1 .. 1e-10, b = A x + 1e-10 r_perp)"),
