@@ -42,6 +42,7 @@ CASES = [
     (1000, 1, 1000, np.float64),       # d = m, single column
     (4099, 129, 130, np.float64),      # ragged fp64, two column tiles
     (777, 3, 5, np.float32),
+    (40000, 64, 2048, np.float64),     # staged placing with 96 KB of LDS per work-group
 ]
 
 
@@ -136,3 +137,26 @@ def test_largest_sketch_size(gpu_lib):
     SAr, Sbr = OS.countsketch_apply(A, b, 11, d)
     assert np.array_equal(SA.astype(np.float64), SAr)
     assert np.array_equal(Sb.astype(np.float64), Sbr)
+
+
+def test_staged_and_direct_placing_agree(gpu_lib):
+    """The bucket sort places a work-group's keys through LDS when they fit
+    (at most 1024 keys per wave-block) and scatters them directly otherwise,
+    one form for a whole batch.  A problem solved alone (staged) and next to
+    a 5,000,000-row problem (whose 1280-key wave-blocks put the batch on the
+    direct scatter) gives the same bits: either way the rows of a bucket are
+    summed in ascending row order."""
+    import torch
+    sns = gpu_lib
+    rng = np.random.default_rng(99)
+    As = _dev(rng.standard_normal((100003, 16)).astype(np.float32), torch)
+    bs = _dev(rng.standard_normal(100003).astype(np.float32), torch)
+    Ab = _dev(rng.standard_normal((5_000_000, 1)).astype(np.float32), torch)
+    bb = _dev(rng.standard_normal(5_000_000).astype(np.float32), torch)
+    x_solo, i_solo = sns.lstsq(As, bs, "count", 64, 21)
+    xs, infos = sns.lstsq_batched([As, Ab], [bs, bb], [64, 8], [21, 5], refine=False)
+    assert i_solo.status == 0 and infos[0].status == 0 and infos[1].status == 0
+    assert np.array_equal(x_solo.cpu().numpy().view(np.uint64), xs[0].cpu().numpy().view(np.uint64))
+    assert i_solo.sketch_resid == infos[0].sketch_resid
+    x_big, _ = sns.lstsq(Ab, bb, "count", 8, 5)
+    assert np.array_equal(x_big.cpu().numpy().view(np.uint64), xs[1].cpu().numpy().view(np.uint64))
