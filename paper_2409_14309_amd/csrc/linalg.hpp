@@ -7,14 +7,39 @@
 
 namespace sns {
 
+// v moved by one data-parallel-primitive step (row shift or row broadcast,
+// `ctrl`), rows outside row_mask and lanes without a source read 0.  Both
+// 32-bit halves move the same way.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over each aligned group of G lanes (G a power of two <= 64); the total
+// is in the group's last lane (other lanes hold partial sums).  Register-only
+// steps in a fixed order: shifts by 1, 2, 4, 8 inside 16-lane rows, then the
+// last lane of row 0 (2) is added into row 1 (3), and lane 31 into rows 2-3.
+template <int G>
+__device__ __forceinline__ double group_sum_last(double s) {
+  if constexpr (G >= 2) s += dpp_f64<0x111, 0xF>(s);   // row_shr:1
+  if constexpr (G >= 4) s += dpp_f64<0x112, 0xF>(s);   // row_shr:2
+  if constexpr (G >= 8) s += dpp_f64<0x114, 0xF>(s);   // row_shr:4
+  if constexpr (G >= 16) s += dpp_f64<0x118, 0xF>(s);  // row_shr:8
+  if constexpr (G >= 32) s += dpp_f64<0x142, 0xA>(s);  // row_bcast:15 into rows 1, 3
+  if constexpr (G >= 64) s += dpp_f64<0x143, 0xC>(s);  // row_bcast:31 into rows 2, 3
+  return s;
+}
+
 // Sum NB values per thread over a work-group of NT threads; tot[0..NB) (LDS)
 // gets the totals, visible to all threads on return.  red: LDS of NB * NT
 // doubles.  The values are transposed through LDS: value c is summed by the
 // P = NT / NB consecutive threads of group c, thread p adding the stored
 // entries p, p + P, ..., p + (NB - 1) P in order (consecutive lanes read
 // consecutive words, so the reads are free of bank conflicts), and the group
-// finishes with an xor-shuffle over its P lanes.  The order is fixed, so the
-// result is reproducible.
+// finishes with register-only lane steps (group_sum_last) over its P lanes.
+// The order is fixed, so the result is reproducible.
 template <int NB, int NT>
 __device__ __forceinline__ void block_reduce_multi(const double (&g)[NB], double* red,
                                                    double* tot) {
@@ -29,14 +54,13 @@ __device__ __forceinline__ void block_reduce_multi(const double (&g)[NB], double
   double s = 0.0;
 #pragma unroll
   for (int q = 0; q < NB; ++q) s += red[c * NT + q * P + p];
-#pragma unroll
-  for (int off = PW / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  s = group_sum_last<PW>(s);
   if constexpr (P <= 64) {
-    if (p == 0) tot[c] = s;
+    if (p == P - 1) tot[c] = s;
   } else {
     // a group spans P / 64 whole waves: combine their totals in wave order
     __syncthreads();
-    if ((t & 63) == 0) red[t >> 6] = s;
+    if ((t & 63) == 63) red[t >> 6] = s;
     __syncthreads();
     if (t < NB) {
       double u = 0.0;

@@ -71,6 +71,38 @@ __host__ __device__ inline int poll_tag(unsigned int epoch, unsigned int step) {
 
 namespace {
 
+// v read from another lane of its 16-lane row by one data-parallel-primitive
+// move (CTRL: a rotation, mirror or quad permutation); both 32-bit halves
+// move the same way.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of t over each aligned group of LPR lanes, in every lane of the group:
+// a butterfly whose partner is at lane distance LPR / 2, ..., 2, 1 (every
+// lane adds the same pairs in the same order, so all lanes hold the same
+// bits).  Steps inside a 16-lane row are register moves: rotations by 8 and
+// 4 (partners i ^ 8 and i ^ 4 once the earlier steps made the values
+// periodic), the half-row mirror for groups of 8 (partner 7 - i), and quad
+// permutations for i ^ 2 and i ^ 1; steps across rows are lane shuffles.
+template <int LPR>
+__device__ __forceinline__ double lanes_allsum(double t) {
+  if constexpr (LPR >= 64) t += __shfl_xor(t, 32, 64);
+  if constexpr (LPR >= 32) t += __shfl_xor(t, 16, 64);
+  if constexpr (LPR >= 16) {
+    t += dpp_move_f64<0x128>(t);  // row_ror:8
+    t += dpp_move_f64<0x124>(t);  // row_ror:4
+  } else if constexpr (LPR == 8) {
+    t += dpp_move_f64<0x141>(t);  // row_half_mirror
+  }
+  if constexpr (LPR >= 4) t += dpp_move_f64<0x4E>(t);  // quad_perm [2, 3, 0, 1]
+  if constexpr (LPR >= 2) t += dpp_move_f64<0xB1>(t);  // quad_perm [1, 0, 3, 2]
+  return t;
+}
+
 
 constexpr int kPassWaves = 4;
 constexpr int kRedSplit = 16;      // partial groups left for the step kernel
@@ -151,8 +183,7 @@ __device__ __forceinline__ void lsqr_pass_item(const LsqrArgs& a, uint32_t loc, 
       for (int c = 0; c < NCH; ++c)
 #pragma unroll
         for (int e = 0; e < VEC; ++e) t0 = fma((double)a0[c][e], w[c][e], t0);
-#pragma unroll
-      for (int off = 1; off < LPR; off <<= 1) t0 += __shfl_xor(t0, off, 64);
+      t0 = lanes_allsum<LPR>(t0);
       const double p0 = t0 - gamma * u0;
 #pragma unroll
       for (int c = 0; c < NCH; ++c)
@@ -187,11 +218,8 @@ __device__ __forceinline__ void lsqr_pass_item(const LsqrArgs& a, uint32_t loc, 
           t0 = fma((double)a0[c][e], w[c][e], t0);
           t1 = fma((double)a1[c][e], w[c][e], t1);
         }
-#pragma unroll
-      for (int off = 1; off < LPR; off <<= 1) {
-        t0 += __shfl_xor(t0, off, 64);
-        t1 += __shfl_xor(t1, off, 64);
-      }
+      t0 = lanes_allsum<LPR>(t0);
+      t1 = lanes_allsum<LPR>(t1);
       const double p0 = t0 - gamma * u0;
       const double p1 = t1 - gamma * u1;
 #pragma unroll
