@@ -284,13 +284,6 @@ __host__ __device__ constexpr size_t place_head_bytes(int waves, uint32_t d) {
   return ((size_t)(waves + 1) * d * 4 + 15) / 16 * 16;
 }
 
-// Start of wave-block wb's entries in bucket k of the sorted order (one past
-// the last wave-block: the end of the bucket).
-__device__ __forceinline__ uint32_t block_start(const SortArgs& a, int64_t wb, uint32_t k) {
-  if (wb >= a.nwb) return a.bucket_ptr[k + 1];
-  return a.bucket_ptr[k] + a.segtot[(wb / a.seg) * a.d + k] + a.counts[wb * a.d + k];
-}
-
 // Staged placing of the kPlaceWaves consecutive wave-blocks of one
 // work-group (all of their keys fit in LDS).  The group's entries of bucket k
 // are one contiguous range of the output (wave-block order, then key order),
