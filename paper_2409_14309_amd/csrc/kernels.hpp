@@ -383,6 +383,9 @@ GatherPlan gather_plan_with(const sns_matrix& A, uint32_t d, bool acc64, int64_t
                             int nseg);
 // Rows a QR panel configuration holds (d <= capacity), or 0 if cfg is unknown.
 int64_t qr_cfg_capacity(int cfg);
+// Most trailing columns per work-group a panel configuration supports (1 or
+// 2; 0 if cfg is unknown).
+int qr_cfg_max_cb(int cfg);
 // The QR job with every problem forced to one panel configuration and
 // trailing-column count (for the tuner).
 QrJob build_qr_job_forced(ArgTable& t, const std::vector<QrArgs>& a, bool f64, int cfg, int cb);

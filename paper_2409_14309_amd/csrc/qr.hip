@@ -184,12 +184,27 @@ __global__ __launch_bounds__(NT) void k_qr_panel(const QrArgs* __restrict__ P, M
 }
 
 // C <- (I - V T V^T)^T C = C - V (T^T (V^T C)) for the trailing columns
-// [j0 + nbw, n] (Sb is the last one), rows [j0, d).  A work-group owns CB
-// columns (trail_cb).  Sweep 1: every thread accumulates its rows' share of
-// W = V^T C in registers (independent loads, no barriers); W is reduced over
-// the group through LDS in a fixed order and multiplied by T^T.  Sweep 2 re-reads V and
-// C and applies the update.
-constexpr int kTrailThreads = 512;
+// [j0 + nbw, n] (Sb is the last one), rows [j0, d).  A work-group of NT
+// threads owns CB columns (trail_cb).  Sweep 1: every thread accumulates its
+// rows' share of W = V^T C in registers (independent loads, no barriers); W
+// is reduced over the group through LDS in a fixed order and multiplied by
+// T^T.  Sweep 2 applies the update from the same registers.
+//
+// Threads of the trailing work-group for panels of NB columns: 1024 for
+// 8-column panels (half the rows per thread of 512 threads, so more loads in
+// flight per work-group: 4.64 -> 4.47 ms for the 4000 x 1000 QR); 512 for
+// 16-column panels (1024 threads with one column per group measured 1.54
+// against 1.50 ms at 2048 x 512) and 4-column panels (1024 threads spill).
+template <int NB>
+constexpr int trail_threads() {
+  return NB == 8 ? 1024 : 512;
+}
+
+// Two columns per work-group need 2 NB x NT doubles of LDS for the reduction.
+template <int NB>
+constexpr int trail_max_cb() {
+  return (size_t)2 * NB * trail_threads<NB>() * sizeof(double) <= 140 * 1024 ? 2 : 1;
+}
 
 // Columns per trailing work item.  It depends only on the problem's own n
 // (the reduction order, hence the rounding, follows it).  Two columns per
@@ -210,10 +225,10 @@ __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t 
 // rows j0 + t + NT r, r < MAXR (d <= MAXR NT): its entries of V and of its
 // columns stay in registers from the first sweep to the second, so V is read
 // from memory once per work-group.
-template <int MAXR, int NB, int CB>
-__global__ __launch_bounds__(kTrailThreads) void k_qr_trailing(const QrArgs* __restrict__ P,
-                                                               Map mp, int64_t j0) {
-  constexpr int NT = kTrailThreads, NV = NB * CB;
+template <int MAXR, int NB, int CB, int NT>
+__global__ __launch_bounds__(NT) void k_qr_trailing(const QrArgs* __restrict__ P, Map mp,
+                                                    int64_t j0) {
+  constexpr int NV = NB * CB;
   __shared__ double red[NV * NT];
   __shared__ double W[NV];
   __shared__ double Wt[NV];
@@ -385,32 +400,40 @@ int qr_cfg_builtin(int64_t d) {
 // built-in rule.
 void qr_shape(int64_t d, int64_t n, int* cfg, int* cb) {
   int c = 0, b = 0;
-  if (tune_qr_lookup(d, n, &c, &b) && qr_cfg_capacity(c) >= d && (b == 1 || b == 2)) {
+  if (tune_qr_lookup(d, n, &c, &b) && qr_cfg_capacity(c) >= d && b >= 1 &&
+      b <= qr_cfg_max_cb(c)) {
     *cfg = c;
     *cb = b;
     return;
   }
   *cfg = qr_cfg_builtin(d);
-  *cb = trail_cb(n);
+  const int mcb = qr_cfg_max_cb(*cfg);
+  *cb = trail_cb(n) < mcb ? trail_cb(n) : mcb;
 }
 
 template <int MAXR, int NB, int NT, int CB>
 void run_panels(const QrJob::Cls& c, hipStream_t st) {
   // rows per thread of the trailing update (d <= MAXR NT, the panel's bound)
-  constexpr int TR = (MAXR * NT + kTrailThreads - 1) / kTrailThreads;
+  constexpr int NTT = trail_threads<NB>();
+  constexpr int TR = (MAXR * NT + NTT - 1) / NTT;
   for (int64_t j0 = 0; j0 < c.maxn; j0 += NB) {
     SNS_LAUNCH("qr_panel", (k_qr_panel<MAXR, NB, NT>), dim3(grid_for((uint32_t)c.count)),
                dim3(NT), 0, st, c.args, c.mone, j0);
     if (c.ntrail)
-      SNS_LAUNCH("qr_trailing", (k_qr_trailing<TR, NB, CB>), dim3(grid_for(c.ntrail)),
-                 dim3(kTrailThreads), 0, st, c.args, c.mtrail, j0);
+      SNS_LAUNCH("qr_trailing", (k_qr_trailing<TR, NB, CB, NTT>), dim3(grid_for(c.ntrail)),
+                 dim3(NTT), 0, st, c.args, c.mtrail, j0);
   }
 }
 
 template <int MAXR, int NB, int NT>
 void run_panels_cb(const QrJob::Cls& c, hipStream_t st) {
-  if (c.cb == 2) run_panels<MAXR, NB, NT, 2>(c, st);
-  else run_panels<MAXR, NB, NT, 1>(c, st);
+  if constexpr (trail_max_cb<NB>() == 2) {
+    if (c.cb == 2) {
+      run_panels<MAXR, NB, NT, 2>(c, st);
+      return;
+    }
+  }
+  run_panels<MAXR, NB, NT, 1>(c, st);
 }
 
 }  // namespace
@@ -473,6 +496,8 @@ QrJob build_qr_job_impl(ArgTable& t, const std::vector<QrArgs>& a, bool f64, int
     j.maxn = x.n > j.maxn ? x.n : j.maxn;
     int c = force_cfg, b = force_cb;
     if (force_cfg < 0) qr_shape(x.d, x.n, &c, &b);
+    if (b > qr_cfg_max_cb(c)) b = qr_cfg_max_cb(c);  // the class's kernels take at most that
+    if (b < 1) b = 1;
     pcfg.push_back(c);
     pcb.push_back(b);
   }
@@ -516,6 +541,15 @@ QrJob build_qr_job(ArgTable& t, const std::vector<QrArgs>& a, bool f64) {
 
 QrJob build_qr_job_forced(ArgTable& t, const std::vector<QrArgs>& a, bool f64, int cfg, int cb) {
   return build_qr_job_impl(t, a, f64, cfg, cb);
+}
+
+int qr_cfg_max_cb(int cfg) {
+  switch (cfg) {
+    case 0: case 1: case 2: return trail_max_cb<16>();
+    case 3: return trail_max_cb<8>();
+    case 4: return trail_max_cb<4>();
+    default: return 0;
+  }
 }
 
 int64_t qr_cfg_capacity(int cfg) {

@@ -72,7 +72,7 @@ bool gather_entry_ok(const sns_tune_gather_entry& e) {
 
 bool qr_entry_ok(const sns_tune_qr_entry& e) {
   return e.d_lo >= 1 && e.d_lo <= e.d_hi && e.n_lo >= 1 && e.n_lo <= e.n_hi &&
-         qr_cfg_capacity(e.cfg) >= e.d_hi && (e.cb == 1 || e.cb == 2);
+         qr_cfg_capacity(e.cfg) >= e.d_hi && e.cb >= 1 && e.cb <= qr_cfg_max_cb(e.cfg);
 }
 
 // Average time of one call of `run` over `reps` calls after one warm-up,
@@ -341,7 +341,7 @@ sns_status sns_tune_qr(int dtype, int64_t d, int64_t n, const void* SA, const vo
   bst.us = -1.0;
   for (int cfg = 0; cfg < 5; ++cfg) {
     if (qr_cfg_capacity(cfg) < d) continue;
-    for (int cb = 1; cb <= 2; ++cb) {
+    for (int cb = 1; cb <= qr_cfg_max_cb(cfg); ++cb) {
       ArgTable t(w.args);
       const QrJob j = build_qr_job_forced(t, qa, dtype == SNS_F64, cfg, cb);
       if (t.bytes() > kTuneArgBytes) return SNS_ERR_OUT_OF_MEMORY;

@@ -151,7 +151,7 @@ def test_tuning_table_round_trip(tmp_path):
     sns.sns_tune_gather_set(sns.TuneGatherEntry(0, 50, 200, 1, 1 << 22, 8, 4, 60.5))
     sns.sns_tune_gather_set(sns.TuneGatherEntry(0, 50, 200, 1, 1 << 22, 16, 2, 55.0))  # replaces
     sns.sns_tune_qr_set(sns.TuneQrEntry(1, 512, 1, 128, 0, 1, 300.25))
-    sns.sns_tune_qr_set(sns.TuneQrEntry(513, 1024, 1, 256, 2, 2, 800.0))
+    sns.sns_tune_qr_set(sns.TuneQrEntry(513, 4096, 1, 256, 3, 2, 800.0))
     p1 = tmp_path / "t1.txt"
     sns.sns_tune_save(str(p1))
     sns.sns_tune_clear()
@@ -164,7 +164,7 @@ def test_tuning_table_round_trip(tmp_path):
                     ["1", "50", "4096", "65535", "16", "1", "64", "2", "7.250"],
                     ["G", "0", "50", "200", "1", "4194304", "16", "2", "55.000"],
                     ["Q", "1", "512", "1", "128", "0", "1", "300.250"],
-                    ["Q", "513", "1024", "1", "256", "2", "2", "800.000"]]
+                    ["Q", "513", "4096", "1", "256", "3", "2", "800.000"]]
     import pytest
     with pytest.raises(sns.SnsError):
         sns.sns_tune_set(sns.TuneEntry(0, 64, 1, 10, 8, 2, 64, 1, 0.0))  # (8, 2) not a pass shape
