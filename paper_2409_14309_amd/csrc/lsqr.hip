@@ -104,7 +104,7 @@ __device__ __forceinline__ double lanes_allsum(double t) {
 }
 
 
-constexpr int kPassWaves = 4;
+constexpr int kPassWaves = 8;
 constexpr int kRedSplit = 16;      // partial groups left for the step kernel
 constexpr int kFuseMaxN = 256;     // n up to which k_lsqr_reduce also runs the step
 constexpr int kRedThreads = 512;  // k_lsqr_reduce work-group (8 waves)
