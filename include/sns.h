@@ -347,7 +347,8 @@ sns_status sns_serve_destroy(sns_server* srv);
 
 /* ------------------------------------------------------------ autotuner --
  * The fused refinement pass has launch-shape parameters (lanes per row,
- * 16-byte chunks per lane, work-groups, rows per step).  The plan for a
+ * 16-byte chunks per lane, work-groups, rows per step, waves per
+ * work-group).  The plan for a
  * problem is taken from a tuning table entry matching its dtype, n and m
  * range; without one, a built-in rule is used.  The tuner times every valid
  * candidate on the caller's matrix with HIP events and reports the fastest;
@@ -360,6 +361,7 @@ typedef struct {
   int64_t m_lo, m_hi;    /* rows covered, inclusive */
   int lpr, nch, grid, unroll;
   double us;             /* measured time of one pass (informational) */
+  int waves;             /* waves per work-group: 4 or 8 (0 in sns_tune_set: 4) */
 } sns_tune_entry;
 
 /* Workspace for sns_tune_pass on A. */
@@ -418,10 +420,11 @@ sns_status sns_tune_qr(int dtype, int64_t d, int64_t n, const void* SA, const vo
 /* The table: add or replace the entry with the same key (pass: dtype, n,
  * m_lo, m_hi; gather: dtype, n, d, m_lo, m_hi; QR: d and n ranges; lookups
  * take the first entry that covers a problem); clear (all three kinds);
- * load (appends; text lines "dtype n m_lo m_hi lpr nch grid unroll us" for
- * the pass, "G dtype n d m_lo m_hi lpr nseg us" for the gather,
- * "Q d_lo d_hi n_lo n_hi cfg cb us" for the QR, '#' comments; a malformed
- * line loads nothing from the file) and save.  Thread-safe. */
+ * load (appends; text lines "dtype n m_lo m_hi lpr nch grid unroll us
+ * [waves]" for the pass, waves 4 when absent; "G dtype n d m_lo m_hi lpr
+ * nseg us" for the gather; "Q d_lo d_hi n_lo n_hi cfg cb us" for the QR;
+ * '#' comments; a malformed line loads nothing from the file) and save.
+ * Thread-safe. */
 sns_status sns_tune_set(const sns_tune_entry* e);
 sns_status sns_tune_gather_set(const sns_tune_gather_entry* e);
 sns_status sns_tune_qr_set(const sns_tune_qr_entry* e);

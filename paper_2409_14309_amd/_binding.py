@@ -68,7 +68,7 @@ class ServeStats(C.Structure):
 class TuneEntry(C.Structure):
     _fields_ = [("dtype", C.c_int), ("n", C.c_int), ("m_lo", C.c_int64), ("m_hi", C.c_int64),
                 ("lpr", C.c_int), ("nch", C.c_int), ("grid", C.c_int), ("unroll", C.c_int),
-                ("us", C.c_double)]
+                ("us", C.c_double), ("waves", C.c_int)]
 
 
 class TuneGatherEntry(C.Structure):

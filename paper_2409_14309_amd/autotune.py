@@ -9,8 +9,8 @@ gather sweep does the same for the CountSketch gather with d = 4n
 (sns_tune_gather: lanes per row, segments per bucket).  The QR sweep times
 the panel configurations and trailing widths on a Gaussian [SA | Sb] of each
 listed (d, n) (sns_tune_qr) and records an entry for exactly that shape;
-other shapes keep the built-in rule.  By default the pass entries of one
-(dtype, n) then share one launch class (one_class_per_width).  The table is written where the Python
+other shapes keep the built-in rule.  By default the 4-wave pass entries of
+one (dtype, n) then share one launch class (one_class_per_width).  The table is written where the Python
 binding loads it from.
 
     python -m paper_2409_14309_amd.autotune [--out PATH] [--quick]
@@ -56,25 +56,31 @@ def sweep(dtype_code: int, ns, ms, reps: int, log):
             e.m_lo, e.m_hi = lo, hi
             out.append(e)
             log(f"dtype {dtype_code} n {n:5d} m {m:8d}: lpr {e.lpr:2d} nch {e.nch} grid {e.grid:4d} "
-                f"unroll {e.unroll}  {e.us:9.2f} us")
+                f"unroll {e.unroll} waves {e.waves}  {e.us:9.2f} us")
             del A, ws
     return out
 
 
 def one_class_per_width(entries):
-    """Give every m range of one (dtype, n) the pass class (lanes per row,
-    chunks per lane, rows per step) of its largest-m entry, keeping each
-    entry's own work-group count.  A batch of problems of one width then
-    runs as one launch class per iteration instead of several (the serving
-    mix measured 2.7 % more solves/s), while the largest problems, where
-    bandwidth matters most, keep their fastest shape."""
+    """Give the 4-wave pass entries of one (dtype, n) the launch class (lanes
+    per row, chunks per lane, rows per step) of the largest of them, each
+    keeping its own work-group count.  4-wave entries cover the problems that
+    may be batched with others (the tuner offers 8-wave work-groups only from
+    2^29 entries up); a batch of one width then runs one pass class per
+    iteration instead of several (the serving mix measured 2.7 % more
+    solves/s).  8-wave entries, for problems that fill the device alone, keep
+    their fastest shape."""
     top = {}
     for e in entries:
+        if e.waves == 8:
+            continue
         k = (e.dtype, e.n)
         if k not in top or e.m_hi > top[k].m_hi:
             top[k] = e
     for e in entries:
-        t = top[(e.dtype, e.n)]
+        t = top.get((e.dtype, e.n))
+        if e.waves == 8 or t is None:
+            continue
         e.lpr, e.nch, e.unroll = t.lpr, t.nch, t.unroll
     return entries
 
@@ -88,14 +94,15 @@ def reclass_file(path: str):
     idx, entries = [], []
     for i, ln in enumerate(lines):
         f = ln.split()
-        if len(f) == 9 and f[0] not in ("#", "G", "Q"):
+        if len(f) in (9, 10) and f[0] not in ("#", "G", "Q"):
             idx.append(i)
             entries.append(TuneEntry(int(f[0]), int(f[1]), int(f[2]), int(f[3]), int(f[4]),
-                                     int(f[5]), int(f[6]), int(f[7]), float(f[8])))
+                                     int(f[5]), int(f[6]), int(f[7]), float(f[8]),
+                                     int(f[9]) if len(f) == 10 else 4))
     one_class_per_width(entries)
     for i, e in zip(idx, entries):
         lines[i] = (f"{e.dtype} {e.n} {e.m_lo} {e.m_hi} {e.lpr} {e.nch} {e.grid} {e.unroll} "
-                    f"{e.us:.3f}")
+                    f"{e.us:.3f} {e.waves}")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
 

@@ -368,6 +368,7 @@ struct LsqrPlan {
   int lpr = 16;     // lanes per row
   int nch = 4;      // column chunks per lane (a chunk is 16 bytes per lane)
   int unroll = 1;   // rows per slot and step (1 or 2)
+  int waves = 4;    // waves per work-group (4 or 8)
 };
 LsqrPlan make_lsqr_plan(const sns_matrix& A);
 // Tuning-table lookup (tune.hip): the entry for (dtype, n, m), if any.

@@ -104,7 +104,6 @@ __device__ __forceinline__ double lanes_allsum(double t) {
 }
 
 
-constexpr int kPassWaves = 8;
 constexpr int kRedSplit = 16;      // partial groups left for the step kernel
 constexpr int kFuseMaxN = 256;     // n up to which k_lsqr_reduce also runs the step
 constexpr int kRedThreads = 512;  // k_lsqr_reduce work-group (8 waves)
@@ -137,14 +136,14 @@ __device__ __forceinline__ void load_row_chunks(const T* __restrict__ row, int l
 // each row i,
 //   t = A[i,:] . w;  u'[i] = t - gamma * uin[i];  z += A[i,:]^T u'[i];
 //   nrm += u'[i]^2.  Per-item z and nrm go to zpart / npart.  A row is spread
-// over LPR lanes (NCH 16-byte chunks each).  uin is b before the first step
-// (the residual pass) and u afterwards.
-template <typename T, int VEC, int LPR, int NCH, int U>
+// over LPR lanes (NCH 16-byte chunks each); a work-group has W waves.  uin
+// is b before the first step (the residual pass) and u afterwards.
+template <typename T, int VEC, int LPR, int NCH, int U, int W>
 __device__ __forceinline__ void lsqr_pass_item(const LsqrArgs& a, uint32_t loc, double* zred_,
                                                double* nred) {
   constexpr int RPW = 64 / LPR;
-  constexpr int CW = LPR * VEC;          // columns per chunk
-  constexpr int NSL = kPassWaves * RPW;  // row slots per group
+  constexpr int CW = LPR * VEC;  // columns per chunk
+  constexpr int NSL = W * RPW;   // row slots per group
   double (*zred)[NCH * CW] = reinterpret_cast<double (*)[NCH * CW]>(zred_);
   const LsqrState* __restrict__ st = a.st;
   if (st->done) return;
@@ -258,27 +257,26 @@ __device__ __forceinline__ void lsqr_pass_item(const LsqrArgs& a, uint32_t loc, 
   for (int col = threadIdx.x; col < n && col < NCH * CW; col += blockDim.x) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < kPassWaves; ++q) s += zred[q][col];
+    for (int q = 0; q < W; ++q) s += zred[q][col];
     a.zpart[(size_t)loc * n + col] = s;
   }
   if (threadIdx.x == 0) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < kPassWaves; ++q) s += nred[q];
+    for (int q = 0; q < W; ++q) s += nred[q];
     a.npart[loc] = s;
   }
 }
 
-template <typename T, int VEC, int LPR, int NCH, int U>
-__global__ __launch_bounds__(kPassWaves * 64) void k_lsqr_pass(const LsqrArgs* __restrict__ P,
-                                                               Map mp) {
+template <typename T, int VEC, int LPR, int NCH, int U, int W>
+__global__ __launch_bounds__(W * 64) void k_lsqr_pass(const LsqrArgs* __restrict__ P, Map mp) {
   constexpr int CW = LPR * VEC;
-  __shared__ double zred[kPassWaves * NCH * CW];
-  __shared__ double nred[kPassWaves];
+  __shared__ double zred[W * NCH * CW];
+  __shared__ double nred[W];
   const uint32_t it = blockIdx.x;
   if (it >= mp.off[mp.nprob]) return;
   const int pi = map_find(mp, it);
-  lsqr_pass_item<T, VEC, LPR, NCH, U>(P[pi], it - mp.off[pi], zred, nred);
+  lsqr_pass_item<T, VEC, LPR, NCH, U, W>(P[pi], it - mp.off[pi], zred, nred);
 }
 
 // The stop state of the iteration just run, posted to the host ring (one
@@ -758,43 +756,52 @@ __global__ void k_lsqr_active(const LsqrArgs* __restrict__ P, int nprob, int* __
   if (threadIdx.x == 0) *out = c;
 }
 
-template <typename T, int VEC, int LPR, int NCH, int U>
+template <typename T, int VEC, int LPR, int NCH, int U, int W>
 void launch_pass_t(const LsqrJob::Cls& c, hipStream_t s) {
-  SNS_LAUNCH("lsqr_pass", (k_lsqr_pass<T, VEC, LPR, NCH, U>), dim3(grid_for(c.items)),
-             dim3(kPassWaves * 64), 0, s, c.args, c.map);
+  SNS_LAUNCH("lsqr_pass", (k_lsqr_pass<T, VEC, LPR, NCH, U, W>), dim3(grid_for(c.items)),
+             dim3(W * 64), 0, s, c.args, c.map);
 }
 
-template <typename T, int VEC, int U>
+template <typename T, int VEC, int U, int W>
 void launch_pass_u(const LsqrJob::Cls& c, hipStream_t s) {
   switch (c.plan.lpr * 16 + c.plan.nch) {
-    case 4 * 16 + 1: launch_pass_t<T, VEC, 4, 1, U>(c, s); break;
-    case 4 * 16 + 2: launch_pass_t<T, VEC, 4, 2, U>(c, s); break;
-    case 4 * 16 + 4: launch_pass_t<T, VEC, 4, 4, U>(c, s); break;
-    case 8 * 16 + 4: launch_pass_t<T, VEC, 8, 4, U>(c, s); break;
-    case 16 * 16 + 1: launch_pass_t<T, VEC, 16, 1, U>(c, s); break;
-    case 16 * 16 + 2: launch_pass_t<T, VEC, 16, 2, U>(c, s); break;
-    case 16 * 16 + 4: launch_pass_t<T, VEC, 16, 4, U>(c, s); break;
-    case 32 * 16 + 1: launch_pass_t<T, VEC, 32, 1, U>(c, s); break;
-    case 32 * 16 + 2: launch_pass_t<T, VEC, 32, 2, U>(c, s); break;
-    case 32 * 16 + 4: launch_pass_t<T, VEC, 32, 4, U>(c, s); break;
-    case 64 * 16 + 1: launch_pass_t<T, VEC, 64, 1, U>(c, s); break;
-    case 64 * 16 + 2: launch_pass_t<T, VEC, 64, 2, U>(c, s); break;
-    case 64 * 16 + 4: launch_pass_t<T, VEC, 64, 4, U>(c, s); break;
-    default: launch_pass_t<T, VEC, 64, 8, U>(c, s); break;
+    case 4 * 16 + 1: launch_pass_t<T, VEC, 4, 1, U, W>(c, s); break;
+    case 4 * 16 + 2: launch_pass_t<T, VEC, 4, 2, U, W>(c, s); break;
+    case 4 * 16 + 4: launch_pass_t<T, VEC, 4, 4, U, W>(c, s); break;
+    case 8 * 16 + 4: launch_pass_t<T, VEC, 8, 4, U, W>(c, s); break;
+    case 16 * 16 + 1: launch_pass_t<T, VEC, 16, 1, U, W>(c, s); break;
+    case 16 * 16 + 2: launch_pass_t<T, VEC, 16, 2, U, W>(c, s); break;
+    case 16 * 16 + 4: launch_pass_t<T, VEC, 16, 4, U, W>(c, s); break;
+    case 32 * 16 + 1: launch_pass_t<T, VEC, 32, 1, U, W>(c, s); break;
+    case 32 * 16 + 2: launch_pass_t<T, VEC, 32, 2, U, W>(c, s); break;
+    case 32 * 16 + 4: launch_pass_t<T, VEC, 32, 4, U, W>(c, s); break;
+    case 64 * 16 + 1: launch_pass_t<T, VEC, 64, 1, U, W>(c, s); break;
+    case 64 * 16 + 2: launch_pass_t<T, VEC, 64, 2, U, W>(c, s); break;
+    case 64 * 16 + 4: launch_pass_t<T, VEC, 64, 4, U, W>(c, s); break;
+    default: launch_pass_t<T, VEC, 64, 8, U, W>(c, s); break;
   }
 }
 
+template <typename T, int VEC, int W>
+void launch_pass_w(const LsqrJob::Cls& c, hipStream_t s) {
+  if (c.plan.unroll == 2) launch_pass_u<T, VEC, 2, W>(c, s);
+  else launch_pass_u<T, VEC, 1, W>(c, s);
+}
+
+// Work-groups of 4 or 8 waves (plan.waves): 8 suit large problems (more rows
+// in flight per compute unit), 4 the small ones, whose work-groups would
+// otherwise hold more row slots than rows.
 template <typename T, int VEC>
 void launch_pass_v(const LsqrJob::Cls& c, hipStream_t s) {
-  if (c.plan.unroll == 2) launch_pass_u<T, VEC, 2>(c, s);
-  else launch_pass_u<T, VEC, 1>(c, s);
+  if (c.plan.waves == 8) launch_pass_w<T, VEC, 8>(c, s);
+  else launch_pass_w<T, VEC, 4>(c, s);
 }
 
 }  // namespace
 
 // Plan: lanes per row (lpr) and 16-byte column chunks per lane (nch) such
 // that lpr * nch * (16 / element size) covers n; work-groups of the pass.
-// SNS_LSQR_PLAN="lpr,nch,grid,unroll" overrides the choice (tuning runs);
+// SNS_LSQR_PLAN="lpr,nch,grid,unroll[,waves]" overrides the choice (tuning runs);
 // an override that does not cover n is ignored.
 LsqrPlan make_lsqr_plan(const sns_matrix& A) {
   LsqrPlan p;
@@ -814,19 +821,21 @@ LsqrPlan make_lsqr_plan(const sns_matrix& A) {
   if (g < 1) g = 1;
   p.grid = (int)g;
   p.unroll = 1;
+  p.waves = 4;
   LsqrPlan t;
   if (tune_lookup(A.dtype, n, A.m, &t) && lsqr_plan_valid(t.lpr, t.nch) &&
       (int64_t)t.lpr * t.nch * vw >= n && t.grid >= 1 && t.grid <= 65535 &&
-      (t.unroll == 1 || t.unroll == 2))
+      (t.unroll == 1 || t.unroll == 2) && (t.waves == 4 || t.waves == 8))
     p = t;
   if (const char* e = getenv("SNS_LSQR_PLAN")) {
-    int a = 0, b = 0, c = 0, d = 1;
-    if (sscanf(e, "%d,%d,%d,%d", &a, &b, &c, &d) >= 3) {
+    int a = 0, b = 0, c = 0, d = 1, w = 4;
+    if (sscanf(e, "%d,%d,%d,%d,%d", &a, &b, &c, &d, &w) >= 3) {
       if (lsqr_plan_valid(a, b) && (int64_t)a * b * vw >= n && c >= 1 && c <= 65535) {
         p.lpr = a;
         p.nch = b;
         p.grid = c;
         p.unroll = d == 2 ? 2 : 1;
+        p.waves = w == 8 ? 8 : 4;
       }
     }
   }
@@ -1009,7 +1018,8 @@ LsqrJob build_lsqr_job(ArgTable& t, const std::vector<LsqrProb>& p, bool f64) {
     std::vector<uint32_t> cnt;
     for (size_t k = i; k < p.size(); ++k) {
       const LsqrPlan& q = p[k].plan;
-      if (used[k] || q.lpr != c.plan.lpr || q.nch != c.plan.nch || q.unroll != c.plan.unroll)
+      if (used[k] || q.lpr != c.plan.lpr || q.nch != c.plan.nch || q.unroll != c.plan.unroll ||
+          q.waves != c.plan.waves)
         continue;
       used[k] = true;
       sub.push_back(p[k].args);

@@ -2,7 +2,8 @@
 // consult.  sns_tune_pass times every valid candidate of the refinement pass
 // (lanes per row and chunks per lane that cover n without more than doubling
 // the padded width, work-group counts from 64 to 4096, one or two rows per
-// step) on the caller's matrix and reports the fastest; sns_tune_gather does
+// step, 4 or 8 waves per work-group, 8 only for problems of at least 2^29
+// entries) on the caller's matrix and reports the fastest; sns_tune_gather does
 // the same for the CountSketch gather (lanes per row, segments per bucket)
 // after one bucket sort, and sns_tune_qr for the blocked Householder QR
 // (panel configuration, trailing columns per work-group) on a given [SA | Sb].
@@ -181,6 +182,7 @@ bool tune_lookup(sns_dtype dt, int64_t n, int64_t m, LsqrPlan* p) {
     p->nch = r.nch;
     p->grid = r.grid;
     p->unroll = r.unroll;
+    p->waves = r.waves;
     return true;
   }
   return false;
@@ -211,6 +213,10 @@ sns_status sns_tune_pass(const sns_matrix* A, int reps, void* workspace, size_t 
   const int vw = (int)(16 / es);
   const int lprs[5] = {4, 8, 16, 32, 64};
   const int nchs[4] = {1, 2, 4, 8};
+  // 8-wave work-groups only for problems that fill the device alone (m n >=
+  // 2^29): in a batch the small problems share the device, and there their
+  // larger work-groups measured slower (serving mix 3086 -> 2676 solves/s)
+  const int max_waves = (int64_t)A->m * A->n >= (int64_t(1) << 29) ? 8 : 4;
   sns_tune_entry b{};
   b.us = -1.0;
   for (int li = 0; li < 5; ++li)
@@ -221,23 +227,26 @@ sns_status sns_tune_pass(const sns_matrix* A, int reps, void* workspace, size_t 
       if (cover >= 2 * A->n && cover > 16) continue;  // more than half of every row padding
       for (int grid = 64; grid <= 4096; grid *= 2) {
         if (grid > 64 && (int64_t)grid * 64 > A->m) break;  // fewer than 64 rows per group
-        for (int unroll = 1; unroll <= 2; ++unroll) {
-          LsqrPlan p;
-          p.lpr = lpr;
-          p.nch = nch;
-          p.grid = grid;
-          p.unroll = unroll;
-          double us = 0.0;
-          s = time_lsqr_pass(*A, p, reps, workspace, ws_bytes, (hipStream_t)stream, &us);
-          if (s != SNS_OK) return s;
-          if (b.us < 0.0 || us < b.us) {
-            b.lpr = lpr;
-            b.nch = nch;
-            b.grid = grid;
-            b.unroll = unroll;
-            b.us = us;
+        for (int unroll = 1; unroll <= 2; ++unroll)
+          for (int waves = 4; waves <= max_waves; waves += 4) {
+            LsqrPlan p;
+            p.lpr = lpr;
+            p.nch = nch;
+            p.grid = grid;
+            p.unroll = unroll;
+            p.waves = waves;
+            double us = 0.0;
+            s = time_lsqr_pass(*A, p, reps, workspace, ws_bytes, (hipStream_t)stream, &us);
+            if (s != SNS_OK) return s;
+            if (b.us < 0.0 || us < b.us) {
+              b.lpr = lpr;
+              b.nch = nch;
+              b.grid = grid;
+              b.unroll = unroll;
+              b.waves = waves;
+              b.us = us;
+            }
           }
-        }
       }
     }
   if (b.us < 0.0) return SNS_ERR_SHAPE;
@@ -382,11 +391,14 @@ sns_status sns_tune_qr_set(const sns_tune_qr_entry* e) {
 sns_status sns_tune_set(const sns_tune_entry* e) {
   if (!e || e->n < 1 || e->m_lo > e->m_hi || !lsqr_plan_valid(e->lpr, e->nch) || e->grid < 1 ||
       e->grid > 65535 || (e->unroll != 1 && e->unroll != 2) ||
-      (e->dtype != SNS_F32 && e->dtype != SNS_F64))
+      (e->dtype != SNS_F32 && e->dtype != SNS_F64) ||
+      (e->waves != 0 && e->waves != 4 && e->waves != 8))
     return SNS_ERR_INVALID_ARG;
+  sns_tune_entry c = *e;
+  if (c.waves == 0) c.waves = 4;
   Table& t = table();
   std::lock_guard<std::mutex> g(t.mu);
-  put(t, *e);
+  put(t, c);
   return SNS_OK;
 }
 
@@ -426,15 +438,17 @@ sns_status sns_tune_load(const char* path) {
       ok = sscanf(p + 1, "%d %d %d %d %d %d %lf", &e.d_lo, &e.d_hi, &e.n_lo, &e.n_hi, &e.cfg,
                   &e.cb, &e.us) == 7 && qr_entry_ok(e);
       if (ok) qrows.push_back(e);
-    } else {  // dtype n m_lo m_hi lpr nch grid unroll us (refinement pass)
+    } else {  // dtype n m_lo m_hi lpr nch grid unroll us [waves] (refinement pass)
       sns_tune_entry e{};
-      ok = sscanf(p, "%d %d %lld %lld %d %d %d %d %lf", &e.dtype, &e.n, &lo, &hi, &e.lpr, &e.nch,
-                  &e.grid, &e.unroll, &e.us) == 9;
+      e.waves = 4;
+      const int got = sscanf(p, "%d %d %lld %lld %d %d %d %d %lf %d", &e.dtype, &e.n, &lo, &hi,
+                             &e.lpr, &e.nch, &e.grid, &e.unroll, &e.us, &e.waves);
+      ok = got == 9 || got == 10;
       e.m_lo = lo;
       e.m_hi = hi;
       ok = ok && e.n >= 1 && e.m_lo <= e.m_hi && lsqr_plan_valid(e.lpr, e.nch) && e.grid >= 1 &&
            e.grid <= 65535 && (e.unroll == 1 || e.unroll == 2) &&
-           (e.dtype == SNS_F32 || e.dtype == SNS_F64);
+           (e.dtype == SNS_F32 || e.dtype == SNS_F64) && (e.waves == 4 || e.waves == 8);
       if (ok) rows.push_back(e);
     }
   }
@@ -454,10 +468,10 @@ sns_status sns_tune_save(const char* path) {
   std::lock_guard<std::mutex> g(t.mu);
   FILE* f = fopen(path, "w");
   if (!f) return SNS_ERR_INVALID_ARG;
-  fprintf(f, "# dtype n m_lo m_hi lpr nch grid unroll us\n");
+  fprintf(f, "# dtype n m_lo m_hi lpr nch grid unroll us waves\n");
   for (const sns_tune_entry& e : t.rows)
-    fprintf(f, "%d %d %lld %lld %d %d %d %d %.3f\n", e.dtype, e.n, (long long)e.m_lo,
-            (long long)e.m_hi, e.lpr, e.nch, e.grid, e.unroll, e.us);
+    fprintf(f, "%d %d %lld %lld %d %d %d %d %.3f %d\n", e.dtype, e.n, (long long)e.m_lo,
+            (long long)e.m_hi, e.lpr, e.nch, e.grid, e.unroll, e.us, e.waves);
   if (!t.grows.empty()) fprintf(f, "# G dtype n d m_lo m_hi lpr nseg us\n");
   for (const sns_tune_gather_entry& e : t.grows)
     fprintf(f, "G %d %d %d %lld %lld %d %d %.3f\n", e.dtype, e.n, e.d, (long long)e.m_lo,

@@ -144,7 +144,7 @@ def test_tuning_table_round_trip(tmp_path):
     sns.load()
     sns.sns_tune_clear()
     a = sns.TuneEntry(0, 256, 1, 1 << 20, 16, 4, 512, 1, 123.5)
-    b = sns.TuneEntry(1, 50, 4096, 65535, 16, 1, 64, 2, 7.25)
+    b = sns.TuneEntry(1, 50, 4096, 65535, 16, 1, 64, 2, 7.25, 8)
     sns.sns_tune_set(a)
     sns.sns_tune_set(b)
     sns.sns_tune_set(sns.TuneEntry(0, 256, 1, 1 << 20, 32, 4, 1024, 2, 99.0))  # replaces a
@@ -160,14 +160,16 @@ def test_tuning_table_round_trip(tmp_path):
     sns.sns_tune_save(str(p2))
     assert p1.read_text() == p2.read_text()
     rows = [ln.split() for ln in p1.read_text().splitlines() if not ln.startswith("#")]
-    assert rows == [["0", "256", "1", "1048576", "32", "4", "1024", "2", "99.000"],
-                    ["1", "50", "4096", "65535", "16", "1", "64", "2", "7.250"],
+    assert rows == [["0", "256", "1", "1048576", "32", "4", "1024", "2", "99.000", "4"],
+                    ["1", "50", "4096", "65535", "16", "1", "64", "2", "7.250", "8"],
                     ["G", "0", "50", "200", "1", "4194304", "16", "2", "55.000"],
                     ["Q", "1", "512", "1", "128", "0", "1", "300.250"],
                     ["Q", "513", "4096", "1", "256", "3", "2", "800.000"]]
     import pytest
     with pytest.raises(sns.SnsError):
         sns.sns_tune_set(sns.TuneEntry(0, 64, 1, 10, 8, 2, 64, 1, 0.0))  # (8, 2) not a pass shape
+    with pytest.raises(sns.SnsError):  # 6 waves per work-group
+        sns.sns_tune_set(sns.TuneEntry(0, 64, 1, 10, 16, 4, 64, 1, 0.0, 6))
     with pytest.raises(sns.SnsError):  # 24 lanes per row: not a power of two
         sns.sns_tune_gather_set(sns.TuneGatherEntry(0, 50, 200, 1, 10, 24, 1, 0.0))
     with pytest.raises(sns.SnsError):  # 128 segments
@@ -177,6 +179,7 @@ def test_tuning_table_round_trip(tmp_path):
     with pytest.raises(sns.SnsError):  # three trailing columns
         sns.sns_tune_qr_set(sns.TuneQrEntry(1, 500, 1, 128, 0, 3, 0.0))
     for text in ("0 64 1 10 16 4 64 1 1.0\n0 64 oops\n",
+                 "0 64 1 10 16 4 64 1 1.0 8\n0 64 11 20 16 4 64 1 1.0 2\n",
                  "G 0 50 200 1 10 16 2 1.0\nG 0 50 200 1 10 12 2 1.0\n",
                  "Q 1 512 1 128 0 1 1.0\nQ 1 9000 1 128 4 1 1.0\n",
                  "Q 1 512 1 128\n"):

@@ -21,9 +21,10 @@ def test_tune_pass_and_tuned_solve(gpu_lib):
     ws = torch.empty(sns.sns_tune_workspace_size(M), dtype=torch.uint8, device="cuda")
     e = sns.sns_tune_pass(M, 3, ws)
     assert e.us > 0 and e.lpr * e.nch * 2 >= 64 and 64 <= e.grid <= 4096 and e.unroll in (1, 2)
+    assert e.waves in (4, 8)
     assert e.m_lo == e.m_hi == 60000 and e.n == 64 and e.dtype == sns.SNS_F64
-    # force an unusual plan for this shape, then solve
-    forced = sns.TuneEntry(sns.SNS_F64, 64, 50000, 70000, 64, 1, 96, 2, 0.0)
+    # force an unusual plan for this shape (8-wave work-groups), then solve
+    forced = sns.TuneEntry(sns.SNS_F64, 64, 50000, 70000, 64, 1, 96, 2, 0.0, 8)
     sns.sns_tune_set(forced)
     try:
         x, info = sns.lstsq(A, b, "count", 256, 5, refine=True, max_iters=8, rtol=0.0)
