@@ -19,12 +19,10 @@ paper tabulates for Philox4x32 and Philox4x64.
 The structure is written once, generically over the word width, so that the
 64-bit instance can be checked against an independent implementation
 (numpy.random.Philox, which is Philox4x64-10) and that check covers the round
-function and key schedule that the 32-bit instance shares.
-
-Parity unpinned: the 32-bit multipliers and Weyl constants.  No known-answer
-vector or independent implementation of Philox4x32-10 is available to check
-them against, so only the shared structure (above) and statistical properties
-pin the 32-bit instance.
+function and key schedule that the 32-bit instance shares.  The 32-bit
+instance, with its own multipliers and Weyl constants, is checked block for
+block against PyTorch's header-only Philox4x32-10 engine, a second
+implementation that shares no code with this one.
 """
 from __future__ import annotations
 
