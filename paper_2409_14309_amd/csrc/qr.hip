@@ -10,11 +10,14 @@
 //                 (for the rank-1 update) and with the earlier Householder
 //                 vectors (for the compact-WY factor T).
 //   k_qr_trailing applies (I - V T V^T)^T to the trailing columns, Sb
-//                 included; each work-group owns one or two columns.
+//                 included; a work-group keeps V in registers and takes
+//                 groups of one (or two) columns in turn.
 // then k_qr_extract copies R out (tiled transposes) and k_qr_finish checks
 // rank and finiteness and solves R x0 = c on one work-group.
 // Reflector convention (LAPACK): beta = -sign(alpha) ||x|| (sign(0) = +1),
 // tau = (beta - alpha) / beta, v = x / (alpha - beta) with v[0] = 1.
+#include <atomic>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "linalg.hpp"
@@ -206,11 +209,13 @@ constexpr int trail_max_cb() {
   return (size_t)2 * NB * trail_threads<NB>() * sizeof(double) <= 140 * 1024 ? 2 : 1;
 }
 
-// Columns per trailing work item.  It depends only on the problem's own n
-// (the reduction order, hence the rounding, follows it).  Two columns per
-// work-group halve the reads of V per column; below n = 384 the halved
-// number of work-groups no longer fills the chip and one column is faster.
-int trail_cb(int64_t n) { return n >= 384 ? 2 : 1; }
+// Columns per trailing group when no tuned entry covers the problem (the
+// reduction order, hence the rounding, follows it).  Since a work-group keeps
+// V for all the groups it takes, one column per group is as fast as two or
+// faster at every measured size (4000 x 1000: 4.04 against 4.28 ms; 3000 x
+// 700: 2.46 against 2.66 ms; 2048 x 512 and 1024 x 256 equal or better),
+// with one exception within 0.3 % (8192 x 600).
+int trail_cb(int64_t) { return 1; }
 
 template <int NB>
 __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t d, int64_t j0,
@@ -220,11 +225,15 @@ __device__ __forceinline__ double v_entry(const double* __restrict__ M, int64_t 
   return i > ja ? M[ja * d + i] : (i == ja ? 1.0 : 0.0);
 }
 
-// One work item per CB trailing columns; a problem owns ceil(n / CB) items,
-// of which the first ceil(ntr / CB) have columns at step j0.  Thread t owns
-// rows j0 + t + NT r, r < MAXR (d <= MAXR NT): its entries of V and of its
-// columns stay in registers from the first sweep to the second, so V is read
-// from memory once per work-group.
+// A problem's trailing columns at step j0 (Sb included) form
+// ceil(ntr / CB) groups of CB; its nit work items take groups loc,
+// loc + nit, ...  (nit is capped so that one problem's items are resident
+// together: a step then runs as one round of work-groups, and V is read once
+// per work-group rather than once per group of columns).  Thread t owns rows
+// j0 + t + NT r, r < MAXR (d <= MAXR NT): its entries of V stay in registers
+// for all of the item's columns, and those of its columns from the first
+// sweep to the second.  Every column's arithmetic (and its reduction order)
+// is the same whichever item takes it.
 template <int MAXR, int NB, int CB, int NT>
 __global__ __launch_bounds__(NT) void k_qr_trailing(const QrArgs* __restrict__ P, Map mp,
                                                     int64_t j0) {
@@ -238,61 +247,81 @@ __global__ __launch_bounds__(NT) void k_qr_trailing(const QrArgs* __restrict__ P
   const int pi = map_find(mp, it);
   const QrArgs& a = P[pi];
   const uint32_t loc = it - mp.off[pi];
+  const uint32_t nit = mp.off[pi + 1] - mp.off[pi];
   const int64_t d = a.d, n = a.n;
   if (j0 >= n) return;
   const int nbw = (int)((n - j0) < NB ? (n - j0) : NB);
   const int64_t ntr = n + 1 - (j0 + nbw);
-  if ((int64_t)loc * CB >= ntr) return;
+  const int64_t ngrp = (ntr + CB - 1) / CB;
+  if ((int64_t)loc >= ngrp) return;  // uniform over the work-group
   double* __restrict__ M = a.M;
   const double* __restrict__ Tg = a.T;
-  const int64_t jc0 = j0 + nbw + (int64_t)loc * CB;
-  int64_t jc[CB];
-  bool ok[CB];
-#pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    jc[c] = jc0 + c;
-    ok[c] = jc[c] <= n;
-  }
-  double v[MAXR][NB], cv[MAXR][CB];
-  double acc[NV];
-#pragma unroll
-  for (int e = 0; e < NV; ++e) acc[e] = 0.0;
+  double v[MAXR][NB];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     const int64_t i = j0 + t + (int64_t)NT * r;
     const bool in = i < d;
 #pragma unroll
     for (int q = 0; q < NB; ++q) v[r][q] = in ? v_entry<NB>(M, d, j0, q, nbw, i) : 0.0;
-#pragma unroll
-    for (int c = 0; c < CB; ++c) cv[r][c] = (in && ok[c]) ? M[jc[c] * d + i] : 0.0;
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-#pragma unroll
-      for (int c = 0; c < CB; ++c) acc[q * CB + c] = fma(v[r][q], cv[r][c], acc[q * CB + c]);
   }
-  block_reduce_multi<NV, NT>(acc, red, W);
-  // W' = T^T W with T upper triangular (column-major NB x NB)
-  if (t < NV) {
-    const int q = t / CB, c = t % CB;
-    double s = 0.0;
-    for (int b2 = 0; b2 <= q && b2 < nbw; ++b2) s += Tg[q * NB + b2] * W[b2 * CB + c];
-    Wt[t] = q < nbw ? s : 0.0;
-  }
-  __syncthreads();
-  double wt[NV];
+  // this thread's entries of the columns of group g (zero past d or n)
+  auto load_cols = [&](int64_t g, double (&dst)[MAXR][CB]) {
 #pragma unroll
-  for (int e = 0; e < NV; ++e) wt[e] = Wt[e];
+    for (int r = 0; r < MAXR; ++r) {
+      const int64_t i = j0 + t + (int64_t)NT * r;
 #pragma unroll
-  for (int r = 0; r < MAXR; ++r) {
-    const int64_t i = j0 + t + (int64_t)NT * r;
-    if (i >= d) continue;
+      for (int c = 0; c < CB; ++c) {
+        const int64_t j = j0 + nbw + g * CB + c;
+        dst[r][c] = (i < d && j <= n) ? M[j * d + i] : 0.0;
+      }
+    }
+  };
+  for (int64_t g = loc; g < ngrp; g += nit) {
+    double cv[MAXR][CB];
+    load_cols(g, cv);
+    const int64_t jc0 = j0 + nbw + g * CB;
+    int64_t jc[CB];
+    bool ok[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-      if (!ok[c]) continue;
-      double s = 0.0;
+      jc[c] = jc0 + c;
+      ok[c] = jc[c] <= n;
+    }
+    double acc[NV];
 #pragma unroll
-      for (int q = 0; q < NB; ++q) s = fma(v[r][q], wt[q * CB + c], s);
-      M[jc[c] * d + i] = cv[r][c] - s;
+    for (int e = 0; e < NV; ++e) acc[e] = 0.0;
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r)
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[q * CB + c] = fma(v[r][q], cv[r][c], acc[q * CB + c]);
+    // (the previous group's reads of W and Wt ended before this reduction's
+    // first barrier)
+    block_reduce_multi<NV, NT>(acc, red, W);
+    // W' = T^T W with T upper triangular (column-major NB x NB)
+    if (t < NV) {
+      const int q = t / CB, c = t % CB;
+      double s = 0.0;
+      for (int b2 = 0; b2 <= q && b2 < nbw; ++b2) s += Tg[q * NB + b2] * W[b2 * CB + c];
+      Wt[t] = q < nbw ? s : 0.0;
+    }
+    __syncthreads();
+    double wt[NV];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) wt[e] = Wt[e];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+      const int64_t i = j0 + t + (int64_t)NT * r;
+      if (i >= d) continue;
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        if (!ok[c]) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) s = fma(v[r][q], wt[q * CB + c], s);
+        M[jc[c] * d + i] = cv[r][c] - s;
+      }
     }
   }
 }
@@ -425,6 +454,54 @@ void run_panels(const QrJob::Cls& c, hipStream_t st) {
   }
 }
 
+// Trailing work-groups of configuration (MAXR, NB, NT) with CB columns that
+// the device holds at once: its CU count times the kernel's occupancy.
+template <int MAXR, int NB, int NT, int CB>
+int trail_resident(int dev) {
+  constexpr int NTT = trail_threads<NB>();
+  constexpr int TR = (MAXR * NT + NTT - 1) / NTT;
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, reinterpret_cast<const void*>(&k_qr_trailing<TR, NB, CB, NTT>), NTT, 0) !=
+          hipSuccess)
+    return 0;
+  return cus * (per > 0 ? per : 1);
+}
+
+template <int MAXR, int NB, int NT>
+int trail_resident_cb(int cb, int dev) {
+  if constexpr (trail_max_cb<NB>() == 2)
+    if (cb == 2) return trail_resident<MAXR, NB, NT, 2>(dev);
+  return trail_resident<MAXR, NB, NT, 1>(dev);
+}
+
+// Cap on the trailing work items of one problem (one round of resident
+// work-groups; 0 = no cap), per device, configuration and width, computed
+// once.
+uint32_t trail_items_cap(int cfg, int cb) {
+  constexpr int kDevs = 64;
+  static std::atomic<int> cache[kDevs][5][2];  // 0 = not yet known, -1 = none
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs || cfg < 0 || cfg > 4 ||
+      cb < 1 || cb > 2)
+    return 0;
+  std::atomic<int>& slot = cache[dev][cfg][cb - 1];
+  int v = slot.load();
+  if (v == 0) {
+    switch (cfg) {
+      case 0: v = trail_resident_cb<2, 16, 256>(cb, dev); break;
+      case 1: v = trail_resident_cb<4, 16, 256>(cb, dev); break;
+      case 2: v = trail_resident_cb<4, 16, 512>(cb, dev); break;
+      case 3: v = trail_resident_cb<8, 8, 512>(cb, dev); break;
+      default: v = trail_resident_cb<16, 4, 512>(cb, dev); break;
+    }
+    if (v <= 0) v = -1;
+    slot.store(v);
+  }
+  return v > 0 ? (uint32_t)v : 0u;
+}
+
 template <int MAXR, int NB, int NT>
 void run_panels_cb(const QrJob::Cls& c, hipStream_t st) {
   if constexpr (trail_max_cb<NB>() == 2) {
@@ -516,7 +593,8 @@ QrJob build_qr_job_impl(ArgTable& t, const std::vector<QrArgs>& a, bool f64, int
       if (pcfg[k] != cfg || pcb[k] != cb) continue;
       sub.push_back(x);
       cone.push_back(1u);
-      ctr.push_back((uint32_t)((x.n + cb - 1) / cb));
+      const uint32_t groups = (uint32_t)((x.n + cb - 1) / cb), cap = trail_items_cap(cfg, cb);
+      ctr.push_back(cap > 0 && groups > cap ? cap : groups);
       maxn = x.n > maxn ? x.n : maxn;
     }
     if (sub.empty()) continue;
