@@ -379,8 +379,9 @@ sns_status sns_tune_pass(const sns_matrix* A, int reps, void* workspace, size_t 
  * entry matches a problem by dtype, n, d and an m range.  The blocked QR
  * (Sec. 1.2 step 3) has a panel configuration (0..4: rows per thread, panel
  * width and threads of the panel work-group, holding d <= 512, 1024, 2048,
- * 4096 and 8192 rows) and trailing columns per work-group (1 or 2); an entry
- * matches by d range and n range.  Both change the order of the sums, so a
+ * 4096 and 8192 rows) and the width of the trailing update's column groups
+ * (1 or 2 columns reduced together; a work-group takes several groups in
+ * turn); an entry matches by d range and n range.  Both change the order of the sums, so a
  * result is reproducible for a given table. */
 typedef struct {
   int dtype;             /* sns_dtype */

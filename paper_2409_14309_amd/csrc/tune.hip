@@ -6,7 +6,7 @@
 // entries) on the caller's matrix and reports the fastest; sns_tune_gather does
 // the same for the CountSketch gather (lanes per row, segments per bucket)
 // after one bucket sort, and sns_tune_qr for the blocked Householder QR
-// (panel configuration, trailing columns per work-group) on a given [SA | Sb].
+// (panel configuration, width of the trailing column groups) on a given [SA | Sb].
 #include <stdio.h>
 #include <string.h>
 
