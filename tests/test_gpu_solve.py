@@ -66,6 +66,29 @@ def test_qr_solve_matches_oracle(gpu_lib, d, n):
     assert abs(info.sketch_resid - rho) <= 1e-12 * max(rho, 1.0)
 
 
+def test_qr_solve_largest_shape(gpu_lib):
+    """The largest QR the library takes, d = 8192 and n = 4096 (a trailing
+    step then has 4097 column groups for 256 resident work-groups, so every
+    work-group takes about 16 in turn).  The oracle's column loop is too slow
+    at this size; the reference is LAPACK's Householder QR of [SA | Sb]
+    (numpy), whose R the oracle's pins show equal to the oracle's entry by
+    entry with the same sign convention.  R is compared element by element,
+    x0 = R^{-1} c and rho = |R[n, n]| from the same factorisation."""
+    import torch
+    from scipy.linalg import solve_triangular
+    d, n = 8192, 4096
+    rng = np.random.default_rng(8192)
+    SA = rng.standard_normal((d, n))
+    Sb = rng.standard_normal(d)
+    x0, R, info = _qr_gpu(gpu_lib, torch, SA, Sb)
+    Ra = np.linalg.qr(np.column_stack([SA, Sb]), mode="r")
+    Rr, c = Ra[:n, :n], Ra[:n, n]
+    xr = solve_triangular(Rr, c)
+    assert info.status == 0
+    _check_r_x0(R, Rr, x0, xr)
+    assert abs(info.sketch_resid - abs(Ra[n, n])) <= 1e-12 * abs(Ra[n, n])
+
+
 def test_qr_solve_fp32_input_and_rank_deficiency(gpu_lib):
     import torch
     rng = np.random.default_rng(11)
