@@ -241,6 +241,8 @@ __global__ __launch_bounds__(NT) void k_qr_trailing(const QrArgs* __restrict__ P
   __shared__ double red[NV * NT];
   __shared__ double W[NV];
   __shared__ double Wt[NV];
+  __shared__ double Ts[NB * NB];
+  static_assert(NB * NB <= NT, "one entry of T per thread");
   const int t = threadIdx.x;
   const uint32_t it = blockIdx.x;
   if (it >= mp.off[mp.nprob]) return;
@@ -255,7 +257,9 @@ __global__ __launch_bounds__(NT) void k_qr_trailing(const QrArgs* __restrict__ P
   const int64_t ngrp = (ntr + CB - 1) / CB;
   if ((int64_t)loc >= ngrp) return;  // uniform over the work-group
   double* __restrict__ M = a.M;
-  const double* __restrict__ Tg = a.T;
+  // T once per work-group for all its column groups (the first reduction's
+  // barriers publish it)
+  if (t < NB * NB) Ts[t] = a.T[t];
   double v[MAXR][NB];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_qr_trailing(const QrArgs* __restrict__ P
     if (t < NV) {
       const int q = t / CB, c = t % CB;
       double s = 0.0;
-      for (int b2 = 0; b2 <= q && b2 < nbw; ++b2) s += Tg[q * NB + b2] * W[b2 * CB + c];
+      for (int b2 = 0; b2 <= q && b2 < nbw; ++b2) s += Ts[q * NB + b2] * W[b2 * CB + c];
       Wt[t] = q < nbw ? s : 0.0;
     }
     __syncthreads();
