@@ -39,6 +39,8 @@ __device__ __forceinline__ double group_sum_last(double s) {
 // entries p, p + P, ..., p + (NB - 1) P in order (consecutive lanes read
 // consecutive words, so the reads are free of bank conflicts), and the group
 // finishes with register-only lane steps (group_sum_last) over its P lanes.
+// When P exceeds a wave, wave c alone sums value c (NT / 64 entries per
+// lane), so the reduction still takes two barriers.
 // The order is fixed, so the result is reproducible.
 template <int NB, int NT>
 __device__ __forceinline__ void block_reduce_multi(const double (&g)[NB], double* red,
@@ -50,22 +52,23 @@ __device__ __forceinline__ void block_reduce_multi(const double (&g)[NB], double
 #pragma unroll
   for (int c = 0; c < NB; ++c) red[c * NT + t] = g[c];
   __syncthreads();
-  const int c = t / P, p = t % P;
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < NB; ++q) s += red[c * NT + q * P + p];
-  s = group_sum_last<PW>(s);
   if constexpr (P <= 64) {
+    const int c = t / P, p = t % P;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) s += red[c * NT + q * P + p];
+    s = group_sum_last<PW>(s);
     if (p == P - 1) tot[c] = s;
   } else {
-    // a group spans P / 64 whole waves: combine their totals in wave order
-    __syncthreads();
-    if ((t & 63) == 63) red[t >> 6] = s;
-    __syncthreads();
-    if (t < NB) {
-      double u = 0.0;
-      for (int w = 0; w < P / 64; ++w) u += red[t * (P / 64) + w];
-      tot[t] = u;
+    // more than a wave per value: wave c alone sums value c, lane l adding
+    // the stored entries l, l + 64, ... in order, then the lanes
+    const int wv = t >> 6, l = t & 63;
+    if (wv < NB) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < NT / 64; ++q) s += red[wv * NT + q * 64 + l];
+      s = group_sum_last<64>(s);
+      if (l == 63) tot[wv] = s;
     }
   }
   __syncthreads();
