@@ -118,14 +118,23 @@ __device__ inline void trsv_lds(const double* __restrict__ C, int64_t ld, int n,
     if (tid < 64) {
       double xi = lane < bw ? x[b0 + lane] : 0.0;
       const double di = lane < bw ? invd[b0 + lane] : 0.0;
-#pragma unroll 8
-      for (int q = 0; q < 64; ++q) {
-        const int jl = UPPER ? 63 - q : q;
-        if (jl < bw) {
-          const double xj = readlane_f64(xi * di, jl);
-          const double cj = blk[jl * 64 + lane];
-          const bool upd = UPPER ? lane < jl : lane > jl;
-          xi = lane == jl ? xj : (upd ? fma(-cj, xj, xi) : xi);
+      // the block's entries are read 16 steps at a time ahead of the steps
+      // that use them, so no step waits for its own LDS read
+      for (int q0 = 0; q0 < 64; q0 += 16) {
+        double cs[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int jl = UPPER ? 63 - (q0 + u) : q0 + u;
+          cs[u] = blk[jl * 64 + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int jl = UPPER ? 63 - (q0 + u) : q0 + u;
+          if (jl < bw) {
+            const double xj = readlane_f64(xi * di, jl);
+            const bool upd = UPPER ? lane < jl : lane > jl;
+            xi = lane == jl ? xj : (upd ? fma(-cs[u], xj, xi) : xi);
+          }
         }
       }
       if (lane < bw) x[b0 + lane] = xi;
