@@ -608,13 +608,23 @@ constexpr int kGemvRows = 8;   // rows per work item (one per wave)
 
 // Dot product of row i of a triangular matrix stored row-contiguously
 // (M[i * n + j]) with vec over j in [j0, j1), by one wave; all lanes get it.
+// Each lane takes the entries j0 + lane, j0 + lane + 64, ... with eight
+// loads in flight and four running sums, combined in a fixed order.
 __device__ __forceinline__ double wave_row_dot(const double* __restrict__ M, int n, int i, int j0,
                                                int j1, const double* __restrict__ vec) {
   const int lane = threadIdx.x & 63;
   const double* row = M + (int64_t)i * n;
-  double s = 0.0;
-  for (int j = j0 + lane; j < j1; j += 64) s = fma(row[j], vec[j], s);
-  return wave_sum(s);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int j = j0 + lane;
+  for (; j + 7 * 64 < j1; j += 8 * 64) {
+    double x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = row[j + 64 * k];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k & 3] = fma(x[k], vec[j + 64 * k], acc[k & 3]);
+  }
+  for (int k = 0; j < j1; j += 64, ++k) acc[k & 3] = fma(row[j], vec[j], acc[k & 3]);
+  return wave_sum((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 // y = X^T (z / beta) - beta v (first step: X^T (z / beta)), z = sum of the
