@@ -688,8 +688,12 @@ __device__ __forceinline__ void lsqr_xtz_item(const LsqrArgs& a, uint32_t loc, d
   if (!*last) return;
   __threadfence();
   // ---- last item: scalars and n-vector updates ----
+  // the items' partial norms are loaded together into LDS (z is no longer
+  // needed), then summed in item order: the same value on every thread
+  for (uint32_t g = t; g < nitems; g += nt) z[g] = a.ypart[g];
+  __syncthreads();
   double a2 = 0.0;
-  for (uint32_t g = 0; g < nitems; ++g) a2 += a.ypart[g];  // same value on every thread
+  for (uint32_t g = 0; g < nitems; ++g) a2 += z[g];
   LsqrState sc = *st;
   (void)lsqr_update(a, sc, ybuf, beta, sqrt(a2), first, nullptr);
   if (t == 0) {
