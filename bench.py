@@ -85,6 +85,7 @@ def kernel_source_hash(*names) -> str:
 # kernels whose launch times the solve bench reports
 REPORTED_KERNELS = ("lsqr_pass", "cs_gather", "sort_count", "scan_segments", "scan_buckets",
                     "sort_place", "sort_scatter", "gauss_mfma", "form_y", "srht_pass1", "srht_pass", "srht_sample",
+                    "srht_vpass1", "srht_vpass",
                     # phases of several launches, each timed as one region
                     "qr", "csr_sketch")
 
@@ -660,12 +661,17 @@ def main():
     fp64_flops_per = {"qr": 2.0 * (n + 1) ** 2 * (d - (n + 1) / 3.0)}
     # Hadamard sketch: the first butterfly pass reads [A | b] and writes the
     # m' x (n + 1) buffer, each later pass reads and writes it, the sampled
-    # rows read d 2^(L - 8 P) rows of it
+    # rows read d 2^(L - 8 P) rows of it.  When b is transformed as a vector
+    # of its own (srht_vpass1 / srht_vpass), the matrix passes carry n columns
+    # and the vector passes read and write the m' values of b.
     L = max(0, (m - 1).bit_length())
     mp = 1 << L
     P = max(1, (L + 7) // 8 - 1)
-    bytes_per["srht_pass1"] = es * m * (n + 1) + es * mp * (n + 1)
-    bytes_per["srht_pass"] = 2.0 * es * mp * (n + 1)
+    cw = n if "srht_vpass1" in kt else n + 1
+    bytes_per["srht_pass1"] = es * m * cw + es * mp * cw
+    bytes_per["srht_pass"] = 2.0 * es * mp * cw
+    bytes_per["srht_vpass1"] = es * m + es * mp
+    bytes_per["srht_vpass"] = 2.0 * es * mp
     bytes_per["srht_sample"] = es * d * (1 << (L - min(L, 8 * P))) * (n + 1) + es * d * (n + 1)
     # SAA-SAS: Y = A R^-1 with R^-1 upper triangular, n (n + 1) / 2 fp64
     # multiply-adds per row of A, on the FP64 matrix cores
@@ -722,7 +728,8 @@ def main():
                        "GBps_with_sort": round(bytes_per["cs_gather"] / ((cs[2] + sort_us) * 1e-6) / 1e9, 1)}
 
     form_y = roofline("form_y") if "form_y" in kt else None
-    hadamard = {k: roofline(k) for k in ("srht_pass1", "srht_pass", "srht_sample") if k in kt} or None
+    hadamard = {k: roofline(k) for k in ("srht_pass1", "srht_pass", "srht_vpass1", "srht_vpass", "srht_sample")
+                if k in kt} or None
 
     # errors of the last solve against an FP64 least-squares solution of the
     # same data, computed on the host after the timed region

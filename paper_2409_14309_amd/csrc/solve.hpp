@@ -13,7 +13,7 @@ constexpr int64_t kMaxRows = (int64_t(1) << 31) - 1;  // row ids fit 31 bits
 constexpr int64_t kMaxD = 16384;      // CountSketch bucket sort (LDS histograms)
 constexpr int64_t kMaxQrD = 8192;     // register-resident QR panels
 constexpr int64_t kMaxCsrN = 4096;    // CSR sketch: one output row per wave in LDS
-constexpr int64_t kMaxHadRows = int64_t(1) << 26;  // SRHT: pass 2 reads d 2^(L-10) rows
+constexpr int64_t kMaxHadRows = int64_t(1) << 26;  // SRHT: work buffers of m' = 2^L padded rows
 
 sns_status check_matrix(const sns_matrix* A);
 sns_status check_sketch(const sns_sketch* sk, const sns_matrix* A);

@@ -1,7 +1,11 @@
 """GPU parity of the Hadamard sketch (SRHT, Sec. 1.2.1) against the oracle.
 
-The device transforms blocks of 2^10 rows of D [A | b] in LDS, then forms
-each sampled row from the block results with fp64 sums.  Bars: integer inputs
+The device transforms D [A | b] in passes of 8 index bits (registers and
+one LDS exchange per block of 256 rows), then forms each sampled row from
+the untransformed top bits with fp64 sums; b is column n of the work buffers,
+or, when n fills whole column tiles (a multiple of 64 fp32 / 32 fp64
+columns), a vector of its own with its own first pass (m' >= 256) and view
+passes.  Bars: integer inputs
 with d a power of four (so d^{-1/2} is a power of two) give bit-exact SA and
 Sb; random inputs agree to a relative Frobenius error of 1e-5 (fp32) / 1e-12
 (fp64), and every entry lies within (2 L + 16) u d^{-1/2} sum_i |[A | b]_i|
@@ -43,8 +47,12 @@ def _sketch(sns, torch, A, b, d, seed):
     return SA.cpu().numpy().astype(np.float64), Sb.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("m,n,d,dt", [(1000, 7, 64, np.float64), (4097, 33, 256, np.float32),
-                                      (20000, 64, 1024, np.float32), (5, 2, 4, np.float64)])
+@pytest.mark.parametrize("m,n,d,dt", [
+    (1000, 7, 64, np.float64), (4097, 33, 256, np.float32), (5, 2, 4, np.float64),
+    # b as a vector of its own: first pass only (m' = 2^15, 2^9), first pass
+    # and one view pass (m' = 2^17), and m' < 256 (the view of pass 1)
+    (20000, 64, 1024, np.float32), (300, 32, 64, np.float64), (70000, 64, 256, np.float32),
+    (100, 64, 64, np.float32)])
 def test_integer_inputs_bit_exact(gpu_lib, m, n, d, dt):
     import torch
     rng = np.random.default_rng(m + n)
