@@ -110,6 +110,15 @@ def test_host_side_argument_checks():
     assert lib.sns_sketch_workspace_size(C.byref(sh), C.byref(Ac), C.byref(nb)) == 3
     Ahuge = sns.Matrix((1 << 26) + 1, 10, 0, 0, fake, 10, None, None, 0)
     assert lib.sns_sketch_workspace_size(C.byref(sh), C.byref(Ahuge), C.byref(nb)) == 2
+    # fp32 column tiles are 64 wide: n = 63 keeps b as column n of m' x 64
+    # buffers; n = 64 moves b to m'-vectors beside m' x 64 buffers (one buffer
+    # of each for m' = 2^10, two from m' = 2^17 on, where a second pass runs)
+    for m, n, want in [(1000, 63, 1024 * 64 * 4), (1000, 64, 1024 * 64 * 4 + 1024 * 4),
+                       (70000, 63, 2 * (1 << 17) * 64 * 4),
+                       (70000, 64, 2 * ((1 << 17) * 64 * 4 + (1 << 17) * 4))]:
+        Ah = sns.Matrix(m, n, 0, 0, fake, n, None, None, 0)
+        assert lib.sns_sketch_workspace_size(C.byref(sh), C.byref(Ah), C.byref(nb)) == 0
+        assert nb.value == want, (m, n, nb.value, want)
     # refine outside 0..2; SAA-SAS and non-sparse sketches are rejected by batches
     Aa = sns.Matrix(1000, 10, 0, 0, fake, 12, None, None, 0)  # 16-byte rows for refinement
     o3 = sns.opts(refine=3, max_iters=5)
