@@ -15,16 +15,17 @@
 // only in those bits (row segments of 32 columns: 128 bytes fp32, two columns
 // per lane; 256 bytes fp64),
 // applies the stages in registers and one LDS exchange, and writes the result
-// back in place of the same rows (pass 1 reads D A, zero-padded; later passes
-// ping-pong between two m' x C buffers, rows padded to 32 values so that
-// every segment is aligned).  b is column n of the work buffers (C = n + 1)
-// when n is not a multiple of the tile width, so it shares the last tile;
-// otherwise it would take a tile of its own with one scattered 4- or 8-byte
-// access per row, and b is transformed as a vector of its own instead (C =
-// n), by the same kernel on views of it: pass 1 as an m x 1 matrix, the pass
-// over bits [lo, lo + nb) as an (m' >> lo) x 2^lo matrix (row-contiguous, so
-// its bits [0, nb) are the vector's bits [lo, lo + nb)).  The stages run in
-// the same order for b as for the columns of A.  The last at most 8 bits
+// back in place of the same rows (pass 1 reads D A or D [A | b], zero-padded;
+// later passes ping-pong between two m' x C buffers, rows padded to 32 values
+// so that every segment is aligned).  b is column n of the work buffers (C =
+// n + 1) when n is not a multiple of the tile width, so it shares the last
+// tile; otherwise it would take a tile of its own with one scattered 4- or
+// 8-byte access per row, and b is transformed as a vector of its own instead
+// (C = n): its first 8 bits by k_srht_vpass1 (for m' < 256, the pass kernel
+// on b as an m x 1 matrix), each later pass over bits [lo, lo + nb) by the
+// pass kernel on b as an (m' >> lo) x 2^lo matrix (row-contiguous, so its
+// bits [0, nb) are the vector's bits [lo, lo + nb)).  The stages run in the
+// same order for b as for the columns of A.  The last at most 8 bits
 // are never transformed in full: each sampled row r is formed directly
 // (k_srht_sample) as the sum over the top index i_top of
 // (-1)^popcount(r_top & i_top) B[(i_top, r_low)], in fp64, scaled by d^{-1/2}.
