@@ -81,21 +81,27 @@ def test_random_inputs_within_tolerance(gpu_lib, m, n, d, dt):
     assert np.all(np.abs(full - ref) <= (2 * L + 16) * u * colsum[None, :] + 1e-300)
 
 
-def test_full_depth_sampled_rows(gpu_lib):
-    """2^21 + 5 rows (m' = 2^22, 4096 block results per sampled row)."""
+@pytest.mark.parametrize("n", [32, 64])
+def test_full_depth_sampled_rows(gpu_lib, n):
+    """2^21 + 5 rows (m' = 2^22: two full passes, 64 rows summed per sampled
+    row); n = 32 keeps b as column n, n = 64 transforms it as a vector."""
     import torch
-    m, n, d = (1 << 21) + 5, 32, 1024
+    m, d = (1 << 21) + 5, 1024
     p = dense_gaussian(m, n, seed=51, dtype=np.float32)
     SA, Sb = _sketch(gpu_lib, torch, p.A, p.b, d, 3)
     mp = OS.hadamard_padded_rows(m)
     rows = OS.hadamard_rows(3, d, mp)
     signs = OS.hadamard_signs(3, m).astype(np.float64)
     Ab = np.column_stack([p.A, p.b]).astype(np.float64)
+    # b's entry on its own, within the entrywise bound of the random cases
+    L = (mp - 1).bit_length()
+    bbound = (2 * L + 16) * 2.0 ** -24 * np.abs(p.b.astype(np.float64)).sum() / math.sqrt(d)
     for k in (0, 1, 511, 1023):
         h = OS.hadamard_sign_matrix(rows[k:k + 1], mp)[0, :m]
         ref = (h * signs) @ Ab / math.sqrt(d)
         got = np.concatenate([SA[k], [Sb[k]]])
         assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), k
+        assert abs(float(Sb[k]) - ref[-1]) <= bbound, k
 
 
 def test_hadamard_solve_reaches_target(gpu_lib):
